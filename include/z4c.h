@@ -1,0 +1,223 @@
+/*
+ * z4c.h -- C ABI of the MI355X (gfx950) Z4c hot-path library (libz4c.so).
+ *
+ * The library evaluates, for a batch of MeshBlocks (a level set of a
+ * block-based oct-tree mesh, Sec. 3.1 of the paper), the right-hand side of
+ * the Z4c formulation of the Einstein equations with matter sources (Sec. 2:
+ * the spacetime is evolved in Z4c with the perfect-fluid ADM projections
+ * rho, S_i, S_ij as sources), discretised with centred finite differences of
+ * order 4 or 6 and Kreiss-Oliger dissipation (Sec. 4.1: 6th-order FD,
+ * kappa1 = 0.02, kappa2 = 0, sigma_KO = 0.5), and advances it by one stage of
+ * a low-storage Runge-Kutta method (Sec. 4.1: RK3; RK4 also supported).
+ *
+ * Conventions
+ *   - G = c = 1.  Every floating-point array is double (FP64) in device
+ *     memory, structure of arrays, x fastest.
+ *   - State: 22 fields in this order: chi, gt_xx, gt_xy, gt_xz, gt_yy,
+ *     gt_yz, gt_zz, Khat, At_xx, At_xy, At_xz, At_yy, At_yz, At_zz, Theta,
+ *     Gt^x, Gt^y, Gt^z, alpha, beta^x, beta^y, beta^z.
+ *   - Matter: 10 fields rho, S_x, S_y, S_z, S_xx, S_xy, S_xz, S_yy, S_yz,
+ *     S_zz (ADM projections, covariant).  A NULL matter pointer means vacuum.
+ *   - Constraints (output): 8 fields H, M_x, M_y, M_z, Theta, Z^x, Z^y, Z^z.
+ *   - Block b stores (nz+2ng)(ny+2ng)(nx+2ng) points per field; point
+ *     (i, j, k), i in [-ng, nx+ng), has element index
+ *       offset + f*field_stride + (i+ng) + (nx+2ng)*((j+ng) + (ny+2ng)*(k+ng))
+ *     for state field f (moffset / coffset for matter / constraints).
+ *   - Interior points are i in [0, nx) etc.; only interior points of an
+ *     output array are written by the stage, RHS and constraint calls.
+ *
+ * Ownership and asynchrony
+ *   - The caller owns every field array.  A plan owns only its device copy
+ *     of the block table, its tile lists, scratch for norm partial sums and
+ *     its captured graphs; all of it is allocated in z4c_plan_create /
+ *     z4c_plan_set_* / on the first z4c_step_graph call, never by
+ *     z4c_rhs, z4c_rk_stage, z4c_constraints, z4c_ghost_fill or z4c_step.
+ *   - Every compute call is asynchronous on the given HIP stream
+ *     (hipStream_t passed as void*, NULL = default stream).
+ *   - A plan must not be used from two host threads at once.
+ *
+ * Errors: every call returns a z4c_status; arguments are validated on the
+ * host before anything is enqueued, so every error path is testable without
+ * a GPU (z4c_plan_create with Z4C_PLAN_NO_DEVICE).  z4c_last_error() gives
+ * a message for the last failure of the calling thread.
+ */
+#ifndef Z4C_H
+#define Z4C_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    Z4C_OK = 0,
+    Z4C_EINVAL = -1,    /* NULL pointer, bad size, bad parameter, aliasing     */
+    Z4C_ENOGHOST = -2,  /* ng < fd_order/2 + 1 for some block                  */
+    Z4C_EALIGN = -3,    /* array pointer not 8-byte aligned                    */
+    Z4C_EHIP = -4,      /* a HIP runtime call or kernel launch failed          */
+    Z4C_ENOTSUP = -5,   /* valid request this build does not implement         */
+    Z4C_ENOMEM = -6,    /* device allocation for plan tables failed            */
+    Z4C_ENODEV = -7     /* plan created without a device cannot launch         */
+} z4c_status;
+
+typedef enum { Z4C_LAPSE_1PLUSLOG = 0, Z4C_LAPSE_HARMONIC = 1, Z4C_LAPSE_FROZEN = 2 } z4c_lapse;
+typedef enum { Z4C_SHIFT_GAMMADRIVER = 0, Z4C_SHIFT_FROZEN = 1 } z4c_shift;
+typedef enum { Z4C_ARITH_FP64 = 0, Z4C_ARITH_FP32 = 1 } z4c_arith;
+typedef enum {
+    Z4C_GHOST_NONE = 0,       /* leave ghost values as they are               */
+    Z4C_GHOST_PERIODIC = 1,   /* each block periodic on itself                */
+    Z4C_GHOST_NEIGHBOUR = 2,  /* same-level neighbour copy, table of 27/block */
+    Z4C_GHOST_FROZEN = 3      /* every ghost from the `frozen` array          */
+} z4c_ghost;
+
+/* Scheme parameters.
+ *   fd_order     4 or 6 (centred first/second derivatives, Sec. 4.1)
+ *   ko_sigma     Kreiss-Oliger strength sigma (Sec. 4.1: 0.5); operator of
+ *                order 2r = fd_order + 2, Q = (-1)^(r+1) sigma/(2^(2r) h) D^(2r)
+ *   kappa1/2     Z4c constraint damping (Sec. 4.1: 0.02 / 0)
+ *   eta          Gamma-driver damping
+ *   lapse        1+log (d_t alpha = -2 alpha Khat + advection), harmonic
+ *                (-alpha^2 Khat) or frozen (no lapse source term)
+ *   shift        Gamma-driver (d_t beta^i = Gt^i - eta beta^i + advection)
+ *                or frozen (no Gt^i source)
+ *   advect_gauge 1: beta^k d_k advection terms on alpha and beta
+ *   chi_floor    chi is replaced by max(chi, chi_floor) in every 1/chi and
+ *                clamped to it after each stage
+ *   alpha_floor  alpha clamped to it after each stage
+ *   arith        FP64: all arithmetic in double.  FP32: stencil differences
+ *                u_m - u_0 are formed in double, then the derivatives,
+ *                dissipation and the pointwise algebra run in float; storage,
+ *                the Runge-Kutta combination and the floors stay double. */
+typedef struct {
+    int fd_order;
+    double ko_sigma, kappa1, kappa2, eta;
+    int lapse, shift, advect_gauge;
+    double chi_floor, alpha_floor;
+    int arith;
+} z4c_params;
+
+/* One MeshBlock (72 bytes). dx, dy, dz > 0; nx, ny, nz >= 1. */
+typedef struct {
+    long long offset;        /* element offset of state field 0, point (-ng,-ng,-ng)   */
+    long long moffset;       /* same for matter field 0 (ignored when matter is NULL)  */
+    long long coffset;       /* same for constraint field 0                            */
+    long long field_stride;  /* elements between consecutive fields of this block      */
+    int nx, ny, nz, ng;
+    double dx, dy, dz;
+} z4c_block;
+
+/* One Runge-Kutta stage in three-register form (u0 = stage state, u1 =
+ * accumulator, u2 = state at the start of the step), k = RHS(u0):
+ *   u1'  = (read_u1 ? u1 : 0) + delta*u0 + eps*dt*k      (stored if write_u1)
+ *   u0'  = g1*u0 + g2*u1' + g3*u2 + beta*dt*k
+ * then on u0': gt <- gt * det(gt)^(-1/3), At <- At - gt tr(At)/3,
+ * chi <- max(chi, chi_floor), alpha <- max(alpha, alpha_floor). */
+typedef struct {
+    double delta, eps, g1, g2, g3, beta;
+    int read_u1, write_u1;
+} z4c_rk_coeffs;
+
+typedef struct z4c_plan z4c_plan;
+
+/* Flags for z4c_plan_create. */
+#define Z4C_PLAN_NO_DEVICE 1   /* validate and build host tables only; no HIP call */
+
+/* Create a plan for `nblocks` blocks described by the HOST array `blocks`
+ * (copied).  Validates every block (sizes, spacings, ghosts >= fd_order/2+1,
+ * offsets >= 0) and the parameters, builds tile lists and uploads them to the
+ * current HIP device.  *out receives the plan (NULL on error). */
+z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, int nblocks,
+                           int flags, z4c_plan **out);
+z4c_status z4c_plan_destroy(z4c_plan *plan);
+
+/* Replace the scheme parameters (same validation as create). */
+z4c_status z4c_plan_set_params(z4c_plan *plan, const z4c_params *params);
+
+/* Same-level neighbour table (HOST, nblocks*27 ints, -1 = outer boundary),
+ * entry [b*27 + (oz+1)*9 + (oy+1)*3 + (ox+1)] = block adjacent to b in
+ * direction (ox, oy, oz).  Neighbours must have equal nx, ny, nz, ng. */
+z4c_status z4c_plan_set_neighbours(z4c_plan *plan, const int *neighbours);
+
+/* Launch shape for the blocks of one size class (nx, ny, nz) (0 = all).
+ * tile_x/y/z: interior points per workgroup, one thread per point
+ * (supported: 8x8x8, 8x8x4); persistent: 0 = one workgroup per tile,
+ * otherwise that many workgroups each take a contiguous run of tiles. */
+typedef struct {
+    int tile_x, tile_y, tile_z;
+    int persistent;
+} z4c_launch;
+z4c_status z4c_plan_set_launch(z4c_plan *plan, int nx, int ny, int nz, const z4c_launch *launch);
+z4c_status z4c_plan_get_launch(const z4c_plan *plan, int nx, int ny, int nz, z4c_launch *launch);
+
+/* d_t u at every interior point (dissipation included) -> rhs (state layout).
+ * u, rhs: device; rhs must not alias u. */
+z4c_status z4c_rhs(z4c_plan *plan, const double *u, const double *matter, double *rhs,
+                   void *stream);
+
+/* Fused RHS + Runge-Kutta stage + algebraic enforcement, interior points.
+ * u0_in and u0_out must differ (neighbouring tiles still read u0_in); u1
+ * may be NULL only if !read_u1 && !write_u1 && g2 == 0; u2 may be NULL only
+ * if g3 == 0; u2 may equal u0_in.  `c` is a host pointer. */
+z4c_status z4c_rk_stage(z4c_plan *plan, const double *u0_in, double *u0_out, double *u1,
+                        const double *u2, const double *matter, const z4c_rk_coeffs *c,
+                        double dt, void *stream);
+
+/* Constraints (Sec. 4.1 monitoring): H = R + 2/3 K^2 - At.At - 16 pi rho,
+ * M_i (conformal form), Theta, Z^i = (Gt^i - Gt_d^i)/2 at interior points into
+ * `cons` (constraint layout, may be NULL) and per-block norms into `norms`
+ * (device, nblocks*16 doubles: for field q, [b*16+2q] = sum |c| dV and
+ * [b*16+2q+1] = sum c^2 dV, dV = dx dy dz), summed in a fixed order. */
+z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter,
+                           double *cons, double *norms, void *stream);
+
+/* Refresh the ghost points of `u` (device): periodic, neighbour (table set
+ * with z4c_plan_set_neighbours; -1 entries take `frozen`), or frozen
+ * (`frozen` device array in the state layout). */
+z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *frozen,
+                          void *stream);
+
+/* One full Runge-Kutta step: for each stage s, z4c_rk_stage then
+ * z4c_ghost_fill(ghost_policy) on the stage output.  Buffers regs[0..3]:
+ * regs[0] holds y_n on entry; regs[1], regs[2] are stage ping-pong buffers;
+ * regs[3] is the accumulator.  Stage s reads regs[in_s] (in_0 = 0) and
+ * writes regs[out_s]: the one of {1, 2} it does not read, except that the
+ * last stage writes regs[0] when its g3 == 0 (it does not read y_n).  The
+ * final state's index is returned in *result (0 for classic RK4, so the
+ * step can be repeated with the same registers). */
+typedef struct {
+    double *regs[4];
+    const double *matter;
+    const z4c_rk_coeffs *table;   /* host, nstages entries */
+    int nstages;
+    double dt;
+    int ghost_policy;
+    const double *frozen;
+} z4c_step_desc;
+z4c_status z4c_step(z4c_plan *plan, const z4c_step_desc *desc, int *result, void *stream);
+
+/* Same as z4c_step, but the whole step (stages + ghost fills) is captured
+ * into a HIP graph on first use (per distinct descriptor, a few cached) and
+ * replayed afterwards: one host call per step. */
+z4c_status z4c_step_graph(z4c_plan *plan, const z4c_step_desc *desc, int *result,
+                          void *stream);
+
+/* Time each supported launch shape per size class on the caller's buffers
+ * (u0 read, u0_out/u1 overwritten at interior points, one RK4-like stage)
+ * and keep the fastest; `reps` timed launches per candidate.  Results are
+ * readable with z4c_plan_get_launch.  Synchronises the stream. */
+z4c_status z4c_plan_autotune(z4c_plan *plan, const double *u0, double *u0_out, double *u1,
+                             const double *matter, int reps, void *stream);
+
+/* Scan the interior of u for non-finite values; *flag = count found (host
+ * int, the call synchronises the stream). */
+z4c_status z4c_check_finite(z4c_plan *plan, const double *u, long long *count, void *stream);
+
+const char *z4c_strerror(z4c_status status);
+const char *z4c_last_error(void);
+
+/* Number of tiles the plan launches per stage (all size classes). */
+long long z4c_plan_tiles(const z4c_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* Z4C_H */

@@ -23,15 +23,18 @@ from paper_2311_04989_amd.workloads import NF, NM, NC, BLOCK_DTYPE, GHOST_NONE, 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "z4c_oracle.c")
 LIB = os.path.join(HERE, "libz4c_oracle.so")
+LIB_EXT = os.path.join(HERE, "libz4c_oracle_ext.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O3, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-               "-fPIC", "-shared", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with gcc (-O3, OpenMP, no FMA contraction), once
+    with double and once with x87 extended precision as working type."""
+    for path, extra in ((LIB, []), (LIB_EXT, ["-DORACLE_EXTENDED"])):
+        if force or not os.path.exists(path):
+            cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                   "-fPIC", "-shared", "-Wall"] + extra + ["-o", path + ".tmp", SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(path + ".tmp", path)
     return LIB
 
 
@@ -66,15 +69,16 @@ SSPRK3 = [
          read_u1=0, write_u1=0),
 ]
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = ctypes.CDLL(LIB)
+def lib(ext: bool = False):
+    """The FP64 oracle, or (ext=True) the same source in extended precision."""
+    if ext not in _libs:
+        path = LIB_EXT if ext else LIB
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_rhs.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_int, dp, dp,
                               dp, ctypes.c_int]
@@ -87,8 +91,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int), dp, dp]
         L.orc_derivs.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, dp, dp]
         L.orc_max_threads.restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[ext] = L
+    return _libs[ext]
 
 
 def _dp(a):
@@ -108,28 +112,29 @@ def max_threads() -> int:
     return int(lib().orc_max_threads())
 
 
-def rhs(batch, u=None, params=None, nthreads: int = 0) -> np.ndarray:
+def rhs(batch, u=None, params=None, nthreads: int = 0, ext: bool = False) -> np.ndarray:
     """Right-hand side of all blocks; ghost entries of the result are 0."""
     u = batch.u if u is None else u
     out = np.zeros_like(u)
     tab = batch.block_table()
     P = _params(params or batch.params)
-    lib().orc_rhs(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u),
+    lib(ext).orc_rhs(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u),
                   _dp(batch.matter), _dp(out), nthreads)
     return out
 
 
 def rk_stage(batch, u0, u0_out, u1, u2, coeffs: dict, dt: float, params=None,
-             nthreads: int = 0):
+             nthreads: int = 0, ext: bool = False):
     tab = batch.block_table()
     P = _params(params or batch.params)
     c = _RK(**coeffs)
-    lib().orc_rk_stage(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u0),
+    lib(ext).orc_rk_stage(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u0),
                        _dp(u0_out), _dp(u1), _dp(u2), _dp(batch.matter), ctypes.byref(c),
                        float(dt), nthreads)
 
 
-def constraints(batch, u=None, params=None, nthreads: int = 0, want_fields: bool = True):
+def constraints(batch, u=None, params=None, nthreads: int = 0, want_fields: bool = True,
+                ext: bool = False):
     """Returns (cons, norms): cons in the 8-field layout (None if not wanted),
     norms of shape (nblocks, 8, 2) = (L1, L2^2) with volume element dx dy dz."""
     u = batch.u if u is None else u
@@ -137,7 +142,7 @@ def constraints(batch, u=None, params=None, nthreads: int = 0, want_fields: bool
     P = _params(params or batch.params)
     cons = np.zeros(batch.total_c) if want_fields else None
     norms = np.zeros(len(batch.blocks) * 16)
-    lib().orc_constraints(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u),
+    lib(ext).orc_constraints(ctypes.byref(P), tab.ctypes.data, len(batch.blocks), _dp(u),
                           _dp(batch.matter), _dp(cons), _dp(norms), nthreads)
     return cons, norms.reshape(len(batch.blocks), 8, 2)
 
@@ -171,7 +176,7 @@ def derivs(block, field: np.ndarray, fd_order: int, ko_sigma: float = 1.0) -> np
     return out.reshape(12, block.nz, block.ny, block.nx)
 
 
-def rk_step(batch, u, table=None, dt=None, params=None, nthreads: int = 0, buffers=None):
+def rk_step(batch, u, table=None, dt=None, params=None, nthreads: int = 0, ext: bool = False):
     """One full Runge-Kutta step of every block with the ghost policy of the
     batch applied after each stage.  Returns the new state (a new array)."""
     table = RK4 if table is None else table
@@ -181,7 +186,7 @@ def rk_step(batch, u, table=None, dt=None, params=None, nthreads: int = 0, buffe
     cur = u
     for s, c in enumerate(table):
         nxt = cur.copy()   # ghosts carried over, interior overwritten
-        rk_stage(batch, cur, nxt, u1, y, c, dt, params=params, nthreads=nthreads)
+        rk_stage(batch, cur, nxt, u1, y, c, dt, params=params, nthreads=nthreads, ext=ext)
         ghost_fill(batch, nxt)
         cur = nxt
     return cur

@@ -30,13 +30,22 @@
  * exactly zero derivatives.
  *
  * Compiled with -ffp-contract=off: no fused multiply-add, every product and
- * sum rounds as written.
+ * sum rounds as written.  The working type `real` is double; the same source
+ * built with -DORACLE_EXTENDED works in x87 extended precision (64-bit
+ * significand) and serves only to measure the FP64 oracle's own rounding
+ * error.  Arrays crossing the interface are always double.
  */
-#include <math.h>
+#include <tgmath.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#endif
+
+#ifdef ORACLE_EXTENDED
+typedef long double real;
+#else
+typedef double real;
 #endif
 
 /* Field indices, state (22). */
@@ -67,7 +76,7 @@ typedef struct {
     int read_u1, write_u1;
 } orc_rk;
 
-static const double PI = 3.14159265358979323846;
+static const real PI = 3.141592653589793238462643383279502884L;
 
 /* Index pairs of a symmetric 3x3 tensor stored as 6 components. */
 static const int SYM_I[6] = {0, 0, 0, 1, 1, 2};
@@ -77,48 +86,49 @@ static const int SYM_J[6] = {0, 1, 2, 1, 2, 2};
  * 1-D stencils on a strided pointer u (u[0] = centre, u[m*s] = m-th neighbour)
  * ------------------------------------------------------------------------ */
 
+/* Input samples are double; every difference below is formed in `real`. */
+#define U(off) ((real)u[(off)])
+
 /* First derivative, centred, order p: antisymmetric pairs u_m - u_-m. */
-static double d1(const double *u, long s, double h, int p)
+static real d1(const double *u, long s, real h, int p)
 {
     if (p == 4)
-        return (8.0 * (u[s] - u[-s]) - (u[2 * s] - u[-2 * s])) / (12.0 * h);
-    return (45.0 * (u[s] - u[-s]) - 9.0 * (u[2 * s] - u[-2 * s]) + (u[3 * s] - u[-3 * s]))
-           / (60.0 * h);
+        return (8 * (U(s) - U(-s)) - (U(2 * s) - U(-2 * s))) / (12 * h);
+    return (45 * (U(s) - U(-s)) - 9 * (U(2 * s) - U(-2 * s)) + (U(3 * s) - U(-3 * s))) / (60 * h);
 }
 
 /* Second derivative, centred, order p: weights sum to zero, so it is written
  * in differences from the centre value. */
-static double d2(const double *u, long s, double h, int p)
+static real d2(const double *u, long s, real h, int p)
 {
-    const double c = u[0];
+    const real c = U(0);
     if (p == 4)
-        return (16.0 * ((u[s] - c) + (u[-s] - c)) - ((u[2 * s] - c) + (u[-2 * s] - c)))
-               / (12.0 * h * h);
-    return (270.0 * ((u[s] - c) + (u[-s] - c)) - 27.0 * ((u[2 * s] - c) + (u[-2 * s] - c))
-            + 2.0 * ((u[3 * s] - c) + (u[-3 * s] - c)))
-           / (180.0 * h * h);
+        return (16 * ((U(s) - c) + (U(-s) - c)) - ((U(2 * s) - c) + (U(-2 * s) - c))) / (12 * h * h);
+    return (270 * ((U(s) - c) + (U(-s) - c)) - 27 * ((U(2 * s) - c) + (U(-2 * s) - c))
+            + 2 * ((U(3 * s) - c) + (U(-3 * s) - c)))
+           / (180 * h * h);
 }
 
 /* Mixed second derivative d_a d_b u = D1_a ( D1_b u ): the first-derivative
  * stencil along a applied to first derivatives along b. */
-static double d1d1(const double *u, long sa, long sb, double ha, double hb, int p)
+static real d1d1(const double *u, long sa, long sb, real ha, real hb, int p)
 {
-    double gp[4] = {0}, gm[4] = {0};
+    real gp[4] = {0}, gm[4] = {0};
     const int q = p / 2;
     for (int m = 1; m <= q; ++m) {
         gp[m] = d1(u + m * sa, sb, hb, p);
         gm[m] = d1(u - m * sa, sb, hb, p);
     }
     if (p == 4)
-        return (8.0 * (gp[1] - gm[1]) - (gp[2] - gm[2])) / (12.0 * ha);
-    return (45.0 * (gp[1] - gm[1]) - 9.0 * (gp[2] - gm[2]) + (gp[3] - gm[3])) / (60.0 * ha);
+        return (8 * (gp[1] - gm[1]) - (gp[2] - gm[2])) / (12 * ha);
+    return (45 * (gp[1] - gm[1]) - 9 * (gp[2] - gm[2]) + (gp[3] - gm[3])) / (60 * ha);
 }
 
-static double binomial(int n, int k)
+static real binomial(int n, int k)
 {
-    double r = 1.0;
+    real r = 1.0;
     for (int i = 1; i <= k; ++i)
-        r = r * (double)(n - k + i) / (double)i;
+        r = r * (real)(n - k + i) / (real)i;
     return r;
 }
 
@@ -126,23 +136,23 @@ static double binomial(int n, int k)
  *   Q u = (-1)^(r+1) sigma / (2^(2r) h) * Delta^(2r) u,
  * Delta^(2r) u_0 = sum_{m != 0} c_m (u_m - u_0),  c_m = (-1)^(m+r) C(2r, r+m).
  * On the highest grid mode (-1)^i it returns exactly -sigma/h * u. */
-static double ko1(const double *u, long s, double h, int p, double sigma)
+static real ko1(const double *u, long s, real h, int p, real sigma)
 {
     const int r = p / 2 + 1;
-    const double c0 = u[0];
-    double acc = 0.0;
+    const real c0 = U(0);
+    real acc = 0;
     for (int m = 1; m <= r; ++m) {
-        const double cm = (((m + r) & 1) ? -1.0 : 1.0) * binomial(2 * r, r + m);
-        acc += cm * ((u[m * s] - c0) + (u[-m * s] - c0));
+        const real cm = (((m + r) & 1) ? -1 : 1) * binomial(2 * r, r + m);
+        acc += cm * ((U(m * s) - c0) + (U(-m * s) - c0));
     }
-    const double sign = ((r + 1) & 1) ? -1.0 : 1.0;
+    const real sign = ((r + 1) & 1) ? -1.0 : 1.0;
     return sign * sigma / (ldexp(1.0, 2 * r) * h) * acc;
 }
 
 /* ---------------------------------------------------------------------------
  * Small tensor helpers (plain 3x3)
  * ------------------------------------------------------------------------ */
-static double det3(const double g[3][3])
+static real det3(const real g[3][3])
 {
     return g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1])
          - g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0])
@@ -150,9 +160,9 @@ static double det3(const double g[3][3])
 }
 
 /* Inverse through the adjugate divided by the actual determinant. */
-static void inv3(const double g[3][3], double gi[3][3])
+static void inv3(const real g[3][3], real gi[3][3])
 {
-    const double d = det3(g);
+    const real d = det3(g);
     gi[0][0] = (g[1][1] * g[2][2] - g[1][2] * g[2][1]) / d;
     gi[0][1] = (g[0][2] * g[2][1] - g[0][1] * g[2][2]) / d;
     gi[0][2] = (g[0][1] * g[1][2] - g[0][2] * g[1][1]) / d;
@@ -164,7 +174,7 @@ static void inv3(const double g[3][3], double gi[3][3])
     gi[2][2] = (g[0][0] * g[1][1] - g[0][1] * g[1][0]) / d;
 }
 
-static void unpack_sym(const double *v6, double t[3][3])
+static void unpack_sym(const real *v6, real t[3][3])
 {
     for (int a = 0; a < 6; ++a) {
         t[SYM_I[a]][SYM_J[a]] = v6[a];
@@ -176,11 +186,11 @@ static void unpack_sym(const double *v6, double t[3][3])
  * Per-point derivative gathering
  * ------------------------------------------------------------------------ */
 typedef struct {
-    double u[NFIELD];          /* centre values                         */
-    double du[NFIELD][3];      /* d_k u_f                               */
-    double ddu[NFIELD][3][3];  /* d_k d_l u_f (only for fields needing it) */
-    double ko[NFIELD];         /* sum over directions of the KO operator */
-    double m[NMATTER];         /* matter at the point (0 if absent)     */
+    real u[NFIELD];          /* centre values                         */
+    real du[NFIELD][3];      /* d_k u_f                               */
+    real ddu[NFIELD][3][3];  /* d_k d_l u_f (only for fields needing it) */
+    real ko[NFIELD];         /* sum over directions of the KO operator */
+    real m[NMATTER];         /* matter at the point (0 if absent)     */
 } point_data;
 
 static int needs_second(int f)
@@ -193,7 +203,7 @@ static void gather(const orc_params *P, const orc_block *B, const double *u,
 {
     const long sx = 1, sy = B->nx + 2 * B->ng, sz = (long)sy * (B->ny + 2 * B->ng);
     const long s[3] = {sx, sy, sz};
-    const double h[3] = {B->dx, B->dy, B->dz};
+    const real h[3] = {B->dx, B->dy, B->dz};
     const int p = P->fd_order;
     const long pt = (long)(i + B->ng) * sx + (long)(j + B->ng) * sy + (long)(k + B->ng) * sz;
     memset(pd, 0, sizeof(*pd));
@@ -207,14 +217,14 @@ static void gather(const orc_params *P, const orc_block *B, const double *u,
                 pd->ddu[f][a][a] = d2(c, s[a], h[a], p);
                 for (int b = a + 1; b < 3; ++b) {
                     /* d_a d_b = D1_a ( D1_b u ) */
-                    const double v = d1d1(c, s[a], s[b], h[a], h[b], p);
+                    const real v = d1d1(c, s[a], s[b], h[a], h[b], p);
                     pd->ddu[f][a][b] = v;
                     pd->ddu[f][b][a] = v;
                 }
             }
         }
         if (want_ko) {
-            double q = 0.0;
+            real q = 0.0;
             for (int a = 0; a < 3; ++a)
                 q += ko1(c, s[a], h[a], p, P->ko_sigma);
             pd->ko[f] = q;
@@ -230,27 +240,27 @@ static void gather(const orc_params *P, const orc_block *B, const double *u,
  * Z4c pointwise algebra
  * ------------------------------------------------------------------------ */
 typedef struct {
-    double g[3][3], gi[3][3], A[3][3];
-    double Gl[3][3][3];   /* Gt_{k ij}  = 1/2 (d_i gt_jk + d_j gt_ik - d_k gt_ij) */
-    double Gu[3][3][3];   /* Gt^k_{ij}  = gt^{kl} Gt_{l ij}                       */
-    double Gd[3];         /* Gt_d^i     = gt^{jk} Gt^i_{jk}                       */
-    double R[3][3];       /* R_ij = Rt_ij + R^chi_ij                             */
-    double Rs;            /* R = chi gt^{ij} R_ij                                */
-    double DDa[3][3];     /* D_i D_j alpha (physical covariant derivative)       */
-    double D2a;           /* chi gt^{ij} D_i D_j alpha                            */
-    double Aup[3][3];     /* At^{ij}                                             */
-    double Amix[3][3];    /* At^i_j = gt^{ik} At_kj                               */
-    double AA;            /* At_ij At^ij                                         */
-    double K;             /* Khat + 2 Theta                                      */
-    double chis;          /* max(chi, chi_floor), used in every 1/chi             */
-    double dchi[3], dalpha[3];
+    real g[3][3], gi[3][3], A[3][3];
+    real Gl[3][3][3];   /* Gt_{k ij}  = 1/2 (d_i gt_jk + d_j gt_ik - d_k gt_ij) */
+    real Gu[3][3][3];   /* Gt^k_{ij}  = gt^{kl} Gt_{l ij}                       */
+    real Gd[3];         /* Gt_d^i     = gt^{jk} Gt^i_{jk}                       */
+    real R[3][3];       /* R_ij = Rt_ij + R^chi_ij                             */
+    real Rs;            /* R = chi gt^{ij} R_ij                                */
+    real DDa[3][3];     /* D_i D_j alpha (physical covariant derivative)       */
+    real D2a;           /* chi gt^{ij} D_i D_j alpha                            */
+    real Aup[3][3];     /* At^{ij}                                             */
+    real Amix[3][3];    /* At^i_j = gt^{ik} At_kj                               */
+    real AA;            /* At_ij At^ij                                         */
+    real K;             /* Khat + 2 Theta                                      */
+    real chis;          /* max(chi, chi_floor), used in every 1/chi             */
+    real dchi[3], dalpha[3];
 } geometry;
 
 static void compute_geometry(const orc_params *P, const point_data *pd, geometry *G)
 {
-    double dg[3][3][3];       /* dg[k][i][j]    = d_k gt_ij        */
-    double ddg[3][3][3][3];   /* ddg[k][l][i][j]= d_k d_l gt_ij    */
-    double dGam[3][3];        /* dGam[j][k]     = d_j Gt^k (evolved) */
+    real dg[3][3][3];       /* dg[k][i][j]    = d_k gt_ij        */
+    real ddg[3][3][3][3];   /* ddg[k][l][i][j]= d_k d_l gt_ij    */
+    real dGam[3][3];        /* dGam[j][k]     = d_j Gt^k (evolved) */
     unpack_sym(&pd->u[GXX], G->g);
     unpack_sym(&pd->u[AXX], G->A);
     inv3(G->g, G->gi);
@@ -266,7 +276,7 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
         for (int k = 0; k < 3; ++k)
             dGam[j][k] = pd->du[GAMX + k][j];
 
-    const double chi = pd->u[CHI];
+    const real chi = pd->u[CHI];
     G->chis = chi > P->chi_floor ? chi : P->chi_floor;
     for (int a = 0; a < 3; ++a) {
         G->dchi[a] = pd->du[CHI][a];
@@ -281,13 +291,13 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
     for (int k = 0; k < 3; ++k)
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                double s = 0.0;
+                real s = 0.0;
                 for (int l = 0; l < 3; ++l)
                     s += G->gi[k][l] * G->Gl[l][i][j];
                 G->Gu[k][i][j] = s;
             }
     for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
+        real s = 0.0;
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k)
                 s += G->gi[j][k] * G->Gu[i][j][k];
@@ -295,23 +305,23 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
     }
 
     /* Conformal Ricci tensor Rt_ij. */
-    double Rt[3][3];
+    real Rt[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            double t1 = 0.0;
+            real t1 = 0.0;
             for (int l = 0; l < 3; ++l)
                 for (int m = 0; m < 3; ++m)
                     t1 += G->gi[l][m] * ddg[l][m][i][j];
-            double t2 = 0.0;
+            real t2 = 0.0;
             for (int k = 0; k < 3; ++k)
                 t2 += G->g[k][i] * dGam[j][k] + G->g[k][j] * dGam[i][k];
-            double t3 = 0.0;
+            real t3 = 0.0;
             for (int k = 0; k < 3; ++k)
                 t3 += G->Gd[k] * (G->Gl[i][j][k] + G->Gl[j][i][k]);
-            double t4 = 0.0;
+            real t4 = 0.0;
             for (int l = 0; l < 3; ++l)
                 for (int m = 0; m < 3; ++m) {
-                    double s = 0.0;
+                    real s = 0.0;
                     for (int k = 0; k < 3; ++k)
                         s += G->Gu[k][l][i] * G->Gl[j][k][m] + G->Gu[k][l][j] * G->Gl[i][k][m]
                            + G->Gu[k][i][m] * G->Gl[k][l][j];
@@ -321,15 +331,15 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
         }
 
     /* Conformal-factor part R^chi_ij. */
-    double DDchi[3][3];
+    real DDchi[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
+            real s = 0.0;
             for (int k = 0; k < 3; ++k)
                 s += G->Gu[k][i][j] * G->dchi[k];
             DDchi[i][j] = pd->ddu[CHI][i][j] - s;
         }
-    double trDDchi = 0.0, dchi2 = 0.0;
+    real trDDchi = 0.0, dchi2 = 0.0;
     for (int l = 0; l < 3; ++l)
         for (int m = 0; m < 3; ++m) {
             trDDchi += G->gi[l][m] * DDchi[l][m];
@@ -337,32 +347,32 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
         }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            const double Rchi = (DDchi[i][j] + G->g[i][j] * trDDchi) / (2.0 * G->chis)
+            const real Rchi = (DDchi[i][j] + G->g[i][j] * trDDchi) / (2.0 * G->chis)
                               - (G->dchi[i] * G->dchi[j] + 3.0 * G->g[i][j] * dchi2)
                                 / (4.0 * G->chis * G->chis);
             G->R[i][j] = Rt[i][j] + Rchi;
         }
-    double trR = 0.0;
+    real trR = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             trR += G->gi[i][j] * G->R[i][j];
     G->Rs = chi * trR;
 
     /* D_i D_j alpha of the physical metric gamma_ij = gt_ij / chi. */
-    double dchi_dalpha = 0.0;
+    real dchi_dalpha = 0.0;
     for (int k = 0; k < 3; ++k)
         for (int l = 0; l < 3; ++l)
             dchi_dalpha += G->gi[k][l] * G->dchi[k] * G->dalpha[l];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
+            real s = 0.0;
             for (int k = 0; k < 3; ++k)
                 s += G->Gu[k][i][j] * G->dalpha[k];
             G->DDa[i][j] = pd->ddu[ALPHA][i][j] - s
                          + (G->dchi[i] * G->dalpha[j] + G->dchi[j] * G->dalpha[i]
                             - G->g[i][j] * dchi_dalpha) / (2.0 * G->chis);
         }
-    double trDDa = 0.0;
+    real trDDa = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             trDDa += G->gi[i][j] * G->DDa[i][j];
@@ -371,17 +381,17 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
     /* Raised / mixed At and its square. */
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
+            real s = 0.0;
             for (int k = 0; k < 3; ++k)
                 for (int l = 0; l < 3; ++l)
                     s += G->gi[i][k] * G->gi[j][l] * G->A[k][l];
             G->Aup[i][j] = s;
-            double t = 0.0;
+            real t = 0.0;
             for (int l = 0; l < 3; ++l)
                 t += G->gi[i][l] * G->A[l][j];
             G->Amix[i][j] = t;
         }
-    double AA = 0.0;
+    real AA = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             AA += G->A[i][j] * G->Aup[i][j];
@@ -390,41 +400,41 @@ static void compute_geometry(const orc_params *P, const point_data *pd, geometry
 }
 
 /* The 22 right-hand sides at one point (KO included). */
-static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIELD])
+static void point_rhs(const orc_params *P, const point_data *pd, real rhs[NFIELD])
 {
     geometry G;
     compute_geometry(P, pd, &G);
-    const double chi = pd->u[CHI], alpha = pd->u[ALPHA], Theta = pd->u[THETA];
-    const double Khat = pd->u[KHAT];
-    const double beta[3] = {pd->u[BETAX], pd->u[BETAY], pd->u[BETAZ]};
-    const double Gam[3] = {pd->u[GAMX], pd->u[GAMY], pd->u[GAMZ]};
-    const double K = G.K;
-    double dbeta[3][3];        /* dbeta[j][i] = d_j beta^i       */
-    double ddbeta[3][3][3];    /* ddbeta[j][k][i] = d_j d_k beta^i */
+    const real chi = pd->u[CHI], alpha = pd->u[ALPHA], Theta = pd->u[THETA];
+    const real Khat = pd->u[KHAT];
+    const real beta[3] = {pd->u[BETAX], pd->u[BETAY], pd->u[BETAZ]};
+    const real Gam[3] = {pd->u[GAMX], pd->u[GAMY], pd->u[GAMZ]};
+    const real K = G.K;
+    real dbeta[3][3];        /* dbeta[j][i] = d_j beta^i       */
+    real ddbeta[3][3][3];    /* ddbeta[j][k][i] = d_j d_k beta^i */
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             dbeta[j][i] = pd->du[BETAX + i][j];
             for (int k = 0; k < 3; ++k)
                 ddbeta[j][k][i] = pd->ddu[BETAX + i][j][k];
         }
-    double divb = 0.0;
+    real divb = 0.0;
     for (int k = 0; k < 3; ++k)
         divb += dbeta[k][k];
 
     /* matter */
-    const double rho = pd->m[M_RHO];
-    const double Si[3] = {pd->m[M_SX], pd->m[M_SY], pd->m[M_SZ]};
-    double Sij[3][3];
+    const real rho = pd->m[M_RHO];
+    const real Si[3] = {pd->m[M_SX], pd->m[M_SY], pd->m[M_SZ]};
+    real Sij[3][3];
     unpack_sym(&pd->m[M_SXX], Sij);
-    double trS = 0.0;
+    real trS = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             trS += G.gi[i][j] * Sij[i][j];
-    const double S = chi * trS;
+    const real S = chi * trS;
 
-    double adv[NFIELD];
+    real adv[NFIELD];
     for (int f = 0; f < NFIELD; ++f) {
-        double s = 0.0;
+        real s = 0.0;
         for (int k = 0; k < 3; ++k)
             s += beta[k] * pd->du[f][k];
         adv[f] = s;
@@ -436,7 +446,7 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
     /* conformal metric */
     for (int a = 0; a < 6; ++a) {
         const int i = SYM_I[a], j = SYM_J[a];
-        double lie = 0.0;
+        real lie = 0.0;
         for (int k = 0; k < 3; ++k)
             lie += G.g[i][k] * dbeta[j][k] + G.g[j][k] * dbeta[i][k];
         rhs[GXX + a] = adv[GXX + a] - 2.0 * alpha * G.A[i][j] + lie
@@ -448,21 +458,21 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
               + alpha * P->kappa1 * (1.0 - P->kappa2) * Theta;
 
     /* traceless conformal extrinsic curvature */
-    double X[3][3];
+    real X[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             X[i][j] = -G.DDa[i][j] + alpha * (G.R[i][j] - 8.0 * PI * Sij[i][j]);
-    double trX = 0.0;
+    real trX = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             trX += G.gi[i][j] * X[i][j];
     for (int a = 0; a < 6; ++a) {
         const int i = SYM_I[a], j = SYM_J[a];
-        const double Xtf = X[i][j] - G.g[i][j] * trX / 3.0;
-        double AAm = 0.0;
+        const real Xtf = X[i][j] - G.g[i][j] * trX / 3.0;
+        real AAm = 0.0;
         for (int k = 0; k < 3; ++k)
             AAm += G.A[i][k] * G.Amix[k][j];
-        double lie = 0.0;
+        real lie = 0.0;
         for (int k = 0; k < 3; ++k)
             lie += G.A[i][k] * dbeta[j][k] + G.A[j][k] * dbeta[i][k];
         rhs[AXX + a] = adv[AXX + a] + chi * Xtf + alpha * (K * G.A[i][j] - 2.0 * AAm) + lie
@@ -475,14 +485,14 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
 
     /* Gamma-tilde */
     for (int i = 0; i < 3; ++i) {
-        double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0, s8 = 0.0;
+        real s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0, s8 = 0.0;
         for (int k = 0; k < 3; ++k)
             s1 += G.Gd[k] * dbeta[k][i];
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k)
                 s2 += G.gi[j][k] * ddbeta[j][k][i];
         for (int j = 0; j < 3; ++j) {
-            double dd = 0.0;
+            real dd = 0.0;
             for (int k = 0; k < 3; ++k)
                 dd += ddbeta[j][k][k];
             s3 += G.gi[i][j] * dd;
@@ -505,7 +515,7 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
     }
 
     /* lapse */
-    double muL_a2;  /* mu_L * alpha^2 */
+    real muL_a2;  /* mu_L * alpha^2 */
     if (P->lapse == 0)
         muL_a2 = 2.0 * alpha;
     else if (P->lapse == 1)
@@ -515,7 +525,7 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
     rhs[ALPHA] = (P->advect_gauge ? adv[ALPHA] : 0.0) - muL_a2 * Khat;
 
     /* shift */
-    const double muS_a2 = P->shift == 0 ? 1.0 : 0.0;
+    const real muS_a2 = P->shift == 0 ? 1.0 : 0.0;
     for (int i = 0; i < 3; ++i)
         rhs[BETAX + i] = (P->advect_gauge ? adv[BETAX + i] : 0.0) + muS_a2 * Gam[i]
                        - P->eta * beta[i];
@@ -524,30 +534,30 @@ static void point_rhs(const orc_params *P, const point_data *pd, double rhs[NFIE
         rhs[f] += pd->ko[f];
 }
 
-static void point_constraints(const orc_params *P, const point_data *pd, double c[NCONS])
+static void point_constraints(const orc_params *P, const point_data *pd, real c[NCONS])
 {
     geometry G;
     compute_geometry(P, pd, &G);
-    const double rho = pd->m[M_RHO];
-    const double Si[3] = {pd->m[M_SX], pd->m[M_SY], pd->m[M_SZ]};
-    double dA[3][3][3];   /* dA[k][i][j] = d_k At_ij */
+    const real rho = pd->m[M_RHO];
+    const real Si[3] = {pd->m[M_SX], pd->m[M_SY], pd->m[M_SZ]};
+    real dA[3][3][3];   /* dA[k][i][j] = d_k At_ij */
     for (int a = 0; a < 6; ++a)
         for (int k = 0; k < 3; ++k)
             dA[k][SYM_I[a]][SYM_J[a]] = dA[k][SYM_J[a]][SYM_I[a]] = pd->du[AXX + a][k];
     c[C_H] = G.Rs + (2.0 / 3.0) * G.K * G.K - G.AA - 16.0 * PI * rho;
     for (int i = 0; i < 3; ++i) {
-        double div = 0.0;
+        real div = 0.0;
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k) {
-                double s = dA[k][i][j];
+                real s = dA[k][i][j];
                 for (int l = 0; l < 3; ++l)
                     s -= G.Gu[l][j][k] * G.A[l][i] + G.Gu[l][j][i] * G.A[k][l];
                 div += G.gi[j][k] * s;
             }
-        double t = 0.0;
+        real t = 0.0;
         for (int j = 0; j < 3; ++j)
             t += G.Amix[j][i] * G.dchi[j];
-        const double dK = pd->du[KHAT][i] + 2.0 * pd->du[THETA][i];
+        const real dK = pd->du[KHAT][i] + 2.0 * pd->du[THETA][i];
         c[C_MX + i] = div - 3.0 / (2.0 * G.chis) * t - (2.0 / 3.0) * dK - 8.0 * PI * Si[i];
     }
     c[C_THETA] = pd->u[THETA];
@@ -558,17 +568,17 @@ static void point_constraints(const orc_params *P, const point_data *pd, double 
 /* ---------------------------------------------------------------------------
  * Algebraic enforcement after a stage: det(gt) = 1, tr(At) = 0, floors.
  * ------------------------------------------------------------------------ */
-static void enforce(const orc_params *P, double v[NFIELD])
+static void enforce(const orc_params *P, real v[NFIELD])
 {
-    double g[3][3], gi[3][3], A[3][3];
+    real g[3][3], gi[3][3], A[3][3];
     unpack_sym(&v[GXX], g);
-    const double f = 1.0 / cbrt(det3(g));
+    const real f = 1.0 / cbrt(det3(g));
     for (int a = 0; a < 6; ++a)
         v[GXX + a] *= f;
     unpack_sym(&v[GXX], g);
     inv3(g, gi);
     unpack_sym(&v[AXX], A);
-    double tr = 0.0;
+    real tr = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             tr += gi[i][j] * A[i][j];
@@ -633,14 +643,14 @@ int orc_rhs(const orc_params *P, const orc_block *blocks, int nb, const double *
         const orc_block *B = &blocks[w[t].b];
         const int k = w[t].k;
         point_data pd;
-        double r[NFIELD];
+        real r[NFIELD];
         for (int j = 0; j < B->ny; ++j)
             for (int i = 0; i < B->nx; ++i) {
                 gather(P, B, u, matter, i, j, k, 1, &pd);
                 point_rhs(P, &pd, r);
                 const long pt = point_index(B, i, j, k);
                 for (int f = 0; f < NFIELD; ++f)
-                    rhs[B->offset + (long long)f * B->field_stride + pt] = r[f];
+                    rhs[B->offset + (long long)f * B->field_stride + pt] = (double)r[f];
             }
     }
     free(w);
@@ -661,7 +671,7 @@ int orc_rk_stage(const orc_params *P, const orc_block *blocks, int nb, const dou
         const orc_block *B = &blocks[w[t].b];
         const int k = w[t].k;
         point_data pd;
-        double r[NFIELD], v[NFIELD];
+        real r[NFIELD], v[NFIELD];
         for (int j = 0; j < B->ny; ++j)
             for (int i = 0; i < B->nx; ++i) {
                 gather(P, B, u0, matter, i, j, k, 1, &pd);
@@ -669,16 +679,17 @@ int orc_rk_stage(const orc_params *P, const orc_block *blocks, int nb, const dou
                 const long pt = point_index(B, i, j, k);
                 for (int f = 0; f < NFIELD; ++f) {
                     const long long e = B->offset + (long long)f * B->field_stride + pt;
-                    const double a1 = c->read_u1 ? u1[e] : 0.0;
-                    const double n1 = a1 + c->delta * pd.u[f] + c->eps * dt * r[f];
-                    v[f] = c->g1 * pd.u[f] + c->g2 * n1 + (c->g3 != 0.0 ? c->g3 * u2[e] : 0.0)
-                         + c->beta * dt * r[f];
+                    const real a1 = c->read_u1 ? (real)u1[e] : 0;
+                    const real epsdt = (real)c->eps * (real)dt, betadt = (real)c->beta * (real)dt;
+                    const real n1 = a1 + (real)c->delta * pd.u[f] + epsdt * r[f];
+                    v[f] = (real)c->g1 * pd.u[f] + (real)c->g2 * n1
+                         + (c->g3 != 0.0 ? (real)c->g3 * (real)u2[e] : 0) + betadt * r[f];
                     if (c->write_u1)
-                        u1[e] = n1;
+                        u1[e] = (double)n1;
                 }
                 enforce(P, v);
                 for (int f = 0; f < NFIELD; ++f)
-                    u0_out[B->offset + (long long)f * B->field_stride + pt] = v[f];
+                    u0_out[B->offset + (long long)f * B->field_stride + pt] = (double)v[f];
             }
     }
     free(w);
@@ -694,20 +705,20 @@ int orc_constraints(const orc_params *P, const orc_block *blocks, int nb, const 
     for (int b = 0; b < nb; ++b) {
         const orc_block *B = &blocks[b];
         const double dV = B->dx * B->dy * B->dz;
-        double l1[NCONS] = {0}, l2[NCONS] = {0};
+        real l1[NCONS] = {0}, l2[NCONS] = {0};
         for (int k = 0; k < B->nz; ++k) {
-            double pl1[NCONS] = {0}, pl2[NCONS] = {0};
+            real pl1[NCONS] = {0}, pl2[NCONS] = {0};
 #pragma omp parallel for reduction(+ : pl1[:NCONS], pl2[:NCONS]) schedule(static)
             for (int j = 0; j < B->ny; ++j) {
                 point_data pd;
-                double cv[NCONS];
+                real cv[NCONS];
                 for (int i = 0; i < B->nx; ++i) {
                     gather(P, B, u, matter, i, j, k, 0, &pd);
                     point_constraints(P, &pd, cv);
                     const long pt = point_index(B, i, j, k);
                     for (int q = 0; q < NCONS; ++q) {
                         if (cons)
-                            cons[B->coffset + (long long)q * B->field_stride + pt] = cv[q];
+                            cons[B->coffset + (long long)q * B->field_stride + pt] = (double)cv[q];
                         pl1[q] += fabs(cv[q]);
                         pl2[q] += cv[q] * cv[q];
                     }
@@ -720,8 +731,8 @@ int orc_constraints(const orc_params *P, const orc_block *blocks, int nb, const 
         }
         if (norms)
             for (int q = 0; q < NCONS; ++q) {
-                norms[b * 16 + 2 * q] = l1[q] * dV;
-                norms[b * 16 + 2 * q + 1] = l2[q] * dV;
+                norms[b * 16 + 2 * q] = (double)(l1[q] * dV);
+                norms[b * 16 + 2 * q + 1] = (double)(l2[q] * dV);
             }
     }
     return 0;
@@ -783,16 +794,16 @@ int orc_derivs(const orc_params *P, const orc_block *B, const double *u, double 
                 const double *c = u + point_index(B, i, j, k);
                 const long o = (long)i + (long)B->nx * (j + (long)B->ny * k);
                 for (int a = 0; a < 3; ++a)
-                    out[a * n + o] = d1(c, s[a], h[a], p);
+                    out[a * n + o] = (double)d1(c, s[a], h[a], p);
                 int q = 3;
                 for (int a = 0; a < 3; ++a)
                     for (int b = a; b < 3; ++b) {
-                        out[q * n + o] = (a == b) ? d2(c, s[a], h[a], p)
-                                                  : d1d1(c, s[a], s[b], h[a], h[b], p);
+                        out[q * n + o] = (double)((a == b) ? d2(c, s[a], h[a], p)
+                                                           : d1d1(c, s[a], s[b], h[a], h[b], p));
                         ++q;
                     }
                 for (int a = 0; a < 3; ++a)
-                    out[(9 + a) * n + o] = ko1(c, s[a], h[a], p, P->ko_sigma);
+                    out[(9 + a) * n + o] = (double)ko1(c, s[a], h[a], p, P->ko_sigma);
             }
     return 0;
 }

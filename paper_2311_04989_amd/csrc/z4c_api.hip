@@ -1,0 +1,972 @@
+// z4c_api.hip -- host side of libz4c.so: argument validation, plans (block
+// tables and tile lists in device memory), launches, Runge-Kutta steps,
+// graph capture of whole steps, launch-shape autotuning.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "z4c_internal.h"
+
+using namespace z4c;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+z4c_status fail(z4c_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+z4c_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return Z4C_EHIP;
+}
+
+#define HIP_TRY(call, what)                        \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess)                      \
+            return hip_fail(e_, what);             \
+    } while (0)
+
+struct LaunchGroup {
+    int tx, ty, tz, persistent;
+    std::vector<Tile> tiles;
+    Tile *tiles_d = nullptr;
+    long long tile_base = 0;
+};
+
+struct SizeClass {
+    int nx, ny, nz;
+    z4c_launch launch;
+    std::vector<int> blocks;
+};
+
+struct StepKey {
+    double *regs[4];
+    const double *matter;
+    const double *frozen;
+    double dt;
+    int nstages, ghost_policy;
+    z4c_rk_coeffs table[8];
+    int version;
+    bool operator==(const StepKey &o) const { return std::memcmp(this, &o, sizeof(StepKey)) == 0; }
+};
+
+struct GraphEntry {
+    StepKey key;
+    hipGraphExec_t exec;
+    int result;
+};
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+z4c_status check_params(const z4c_params *p)
+{
+    if (!p)
+        return fail(Z4C_EINVAL, "params is NULL");
+    if (p->fd_order != 4 && p->fd_order != 6)
+        return fail(Z4C_EINVAL, "fd_order must be 4 or 6");
+    if (!(std::isfinite(p->ko_sigma) && p->ko_sigma >= 0.0))
+        return fail(Z4C_EINVAL, "ko_sigma must be finite and >= 0");
+    if (!std::isfinite(p->kappa1) || !std::isfinite(p->kappa2) || !std::isfinite(p->eta))
+        return fail(Z4C_EINVAL, "kappa1, kappa2, eta must be finite");
+    if (p->lapse < 0 || p->lapse > 2 || p->shift < 0 || p->shift > 1)
+        return fail(Z4C_EINVAL, "unknown lapse or shift condition");
+    if (p->advect_gauge != 0 && p->advect_gauge != 1)
+        return fail(Z4C_EINVAL, "advect_gauge must be 0 or 1");
+    if (!(p->chi_floor > 0.0) || !(p->alpha_floor >= 0.0) || !std::isfinite(p->chi_floor)
+        || !std::isfinite(p->alpha_floor))
+        return fail(Z4C_EINVAL, "chi_floor must be > 0 and alpha_floor >= 0");
+    if (p->arith != Z4C_ARITH_FP64 && p->arith != Z4C_ARITH_FP32)
+        return fail(Z4C_EINVAL, "arith must be FP64 or FP32");
+    return Z4C_OK;
+}
+
+z4c_status check_block(const z4c_block &b, int idx, int fd_order)
+{
+    char buf[160];
+    if (b.nx < 1 || b.ny < 1 || b.nz < 1) {
+        std::snprintf(buf, sizeof buf, "block %d: nx, ny, nz must be >= 1", idx);
+        return fail(Z4C_EINVAL, buf);
+    }
+    if (b.ng < fd_order / 2 + 1) {
+        std::snprintf(buf, sizeof buf, "block %d: ng = %d < fd_order/2 + 1 = %d", idx, b.ng,
+                      fd_order / 2 + 1);
+        return fail(Z4C_ENOGHOST, buf);
+    }
+    if (!(b.dx > 0.0 && b.dy > 0.0 && b.dz > 0.0) || !std::isfinite(b.dx) || !std::isfinite(b.dy)
+        || !std::isfinite(b.dz)) {
+        std::snprintf(buf, sizeof buf, "block %d: grid spacings must be finite and > 0", idx);
+        return fail(Z4C_EINVAL, buf);
+    }
+    const long long ex = b.nx + 2LL * b.ng, ey = b.ny + 2LL * b.ng, ez = b.nz + 2LL * b.ng;
+    const long long npts = ex * ey * ez;
+    if (npts > INT_MAX) {
+        std::snprintf(buf, sizeof buf, "block %d: more than 2^31-1 stored points", idx);
+        return fail(Z4C_EINVAL, buf);
+    }
+    if (b.offset < 0 || b.moffset < 0 || b.coffset < 0 || b.field_stride < npts) {
+        std::snprintf(buf, sizeof buf,
+                      "block %d: offsets must be >= 0 and field_stride >= stored points", idx);
+        return fail(Z4C_EINVAL, buf);
+    }
+    return Z4C_OK;
+}
+
+}  // namespace
+
+namespace z4c {
+void block_factors(const z4c_block &b, int fd_order, double sigma, double out[12])
+{
+    const double h[3] = {b.dx, b.dy, b.dz};
+    const double c1 = fd_order == 4 ? 12.0 : 60.0;
+    const double c2 = fd_order == 4 ? 12.0 : 180.0;
+    const double cko = fd_order == 4 ? sigma / 64.0 : -sigma / 256.0;
+    double i1[3];
+    for (int a = 0; a < 3; ++a) {
+        i1[a] = 1.0 / (c1 * h[a]);
+        out[a] = i1[a];
+        out[3 + a] = 1.0 / (c2 * h[a] * h[a]);
+        out[9 + a] = cko / h[a];
+    }
+    out[6] = i1[0] * i1[1];
+    out[7] = i1[0] * i1[2];
+    out[8] = i1[1] * i1[2];
+}
+}  // namespace z4c
+
+struct z4c_plan {
+    z4c_params params{};
+    bool device = false;
+    int nblocks = 0;
+    std::vector<z4c_block> blocks;
+    z4c_block *blocks_d = nullptr;
+    double *fac64_d = nullptr;
+    float *fac32_d = nullptr;
+    std::vector<SizeClass> classes;
+    std::vector<LaunchGroup> groups;
+    long long total_tiles = 0;
+    long long *tile_start_d = nullptr;
+    int *tile_count_d = nullptr;
+    double *partial_d = nullptr;
+    long long *ghost_start_d = nullptr;
+    long long total_ghost = 0;
+    int *nbr_d = nullptr;
+    bool has_nbr = false;
+    bool periodic_ok = true;   // every block has nx, ny, nz >= ng
+    long long *pt_start_d = nullptr;
+    long long total_pts = 0;
+    unsigned long long *count_d = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    int version = 0;
+    int num_cus = 256;
+
+    void free_groups()
+    {
+        for (auto &g : groups)
+            if (g.tiles_d)
+                (void)hipFree(g.tiles_d);
+        groups.clear();
+        if (tile_start_d)
+            (void)hipFree(tile_start_d);
+        if (tile_count_d)
+            (void)hipFree(tile_count_d);
+        if (partial_d)
+            (void)hipFree(partial_d);
+        tile_start_d = nullptr;
+        tile_count_d = nullptr;
+        partial_d = nullptr;
+    }
+    void clear_graphs()
+    {
+        for (auto &g : graphs)
+            (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+};
+
+namespace {
+
+z4c_status upload_factors(z4c_plan *P)
+{
+    if (!P->device)
+        return Z4C_OK;
+    std::vector<double> f64(12 * (size_t)P->nblocks);
+    std::vector<float> f32(12 * (size_t)P->nblocks);
+    for (int b = 0; b < P->nblocks; ++b) {
+        block_factors(P->blocks[b], P->params.fd_order, P->params.ko_sigma, &f64[12 * (size_t)b]);
+        for (int q = 0; q < 12; ++q)
+            f32[12 * (size_t)b + q] = (float)f64[12 * (size_t)b + q];
+    }
+    if (!P->fac64_d)
+        HIP_TRY(hipMalloc(&P->fac64_d, sizeof(double) * f64.size()), "hipMalloc(factors)");
+    if (!P->fac32_d)
+        HIP_TRY(hipMalloc(&P->fac32_d, sizeof(float) * f32.size()), "hipMalloc(factors)");
+    HIP_TRY(hipMemcpy(P->fac64_d, f64.data(), sizeof(double) * f64.size(), hipMemcpyHostToDevice),
+            "hipMemcpy(factors)");
+    HIP_TRY(hipMemcpy(P->fac32_d, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice),
+            "hipMemcpy(factors)");
+    return Z4C_OK;
+}
+
+// Build launch groups from the size classes and upload tile lists.
+z4c_status build_groups(z4c_plan *P)
+{
+    P->free_groups();
+    P->clear_graphs();
+    ++P->version;
+    std::map<std::vector<int>, int> gidx;
+    std::vector<long long> tstart(P->nblocks, 0);
+    std::vector<int> tcount(P->nblocks, 0);
+    for (const SizeClass &c : P->classes) {
+        const std::vector<int> key = {c.launch.tile_x, c.launch.tile_y, c.launch.tile_z,
+                                      c.launch.persistent};
+        auto it = gidx.find(key);
+        int gi;
+        if (it == gidx.end()) {
+            gi = (int)P->groups.size();
+            gidx[key] = gi;
+            LaunchGroup g;
+            g.tx = c.launch.tile_x;
+            g.ty = c.launch.tile_y;
+            g.tz = c.launch.tile_z;
+            g.persistent = c.launch.persistent;
+            P->groups.push_back(g);
+        } else {
+            gi = it->second;
+        }
+        LaunchGroup &g = P->groups[gi];
+        for (int b : c.blocks) {
+            const z4c_block &B = P->blocks[b];
+            tstart[b] = (long long)g.tiles.size();   // relative for now
+            int n = 0;
+            for (int k0 = 0; k0 < B.nz; k0 += g.tz)
+                for (int j0 = 0; j0 < B.ny; j0 += g.ty)
+                    for (int i0 = 0; i0 < B.nx; i0 += g.tx) {
+                        g.tiles.push_back(Tile{b, i0, j0, k0});
+                        ++n;
+                    }
+            tcount[b] = n;
+        }
+    }
+    long long base = 0;
+    std::vector<int> block_group(P->nblocks, 0);
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        P->groups[gi].tile_base = base;
+        base += (long long)P->groups[gi].tiles.size();
+    }
+    for (size_t ci = 0; ci < P->classes.size(); ++ci) {
+        const SizeClass &c = P->classes[ci];
+        const std::vector<int> key = {c.launch.tile_x, c.launch.tile_y, c.launch.tile_z,
+                                      c.launch.persistent};
+        const int gi = gidx[key];
+        for (int b : c.blocks)
+            tstart[b] += P->groups[gi].tile_base;
+    }
+    P->total_tiles = base;
+    if (!P->device)
+        return Z4C_OK;
+    for (auto &g : P->groups) {
+        HIP_TRY(hipMalloc(&g.tiles_d, sizeof(Tile) * std::max<size_t>(1, g.tiles.size())),
+                "hipMalloc(tiles)");
+        HIP_TRY(hipMemcpy(g.tiles_d, g.tiles.data(), sizeof(Tile) * g.tiles.size(),
+                          hipMemcpyHostToDevice),
+                "hipMemcpy(tiles)");
+    }
+    HIP_TRY(hipMalloc(&P->tile_start_d, sizeof(long long) * P->nblocks), "hipMalloc");
+    HIP_TRY(hipMalloc(&P->tile_count_d, sizeof(int) * P->nblocks), "hipMalloc");
+    HIP_TRY(hipMemcpy(P->tile_start_d, tstart.data(), sizeof(long long) * P->nblocks,
+                      hipMemcpyHostToDevice),
+            "hipMemcpy");
+    HIP_TRY(hipMemcpy(P->tile_count_d, tcount.data(), sizeof(int) * P->nblocks,
+                      hipMemcpyHostToDevice),
+            "hipMemcpy");
+    HIP_TRY(hipMalloc(&P->partial_d, sizeof(double) * 16 * std::max<long long>(1, base)),
+            "hipMalloc(partial)");
+    return Z4C_OK;
+}
+
+StageArgs base_args(const z4c_plan *P)
+{
+    StageArgs a{};
+    a.blocks = P->blocks_d;
+    a.fac64 = P->fac64_d;
+    a.fac32 = P->fac32_d;
+    a.ko_sigma = P->params.ko_sigma;
+    a.kappa1 = P->params.kappa1;
+    a.kappa2 = P->params.kappa2;
+    a.eta = P->params.eta;
+    a.chi_floor = P->params.chi_floor;
+    a.alpha_floor = P->params.alpha_floor;
+    a.lapse = P->params.lapse;
+    a.shift = P->params.shift;
+    a.advect_gauge = P->params.advect_gauge;
+    return a;
+}
+
+z4c_status run_groups(z4c_plan *P, int mode, int arith, StageArgs a, hipStream_t s)
+{
+    for (const auto &g : P->groups) {
+        a.tiles = g.tiles_d;
+        a.ntiles = (int)g.tiles.size();
+        a.persistent = g.persistent;
+        a.tile_base = g.tile_base;
+        const hipError_t e = launch_stage(mode, P->params.fd_order, arith, g.tx, g.ty, g.tz, a, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "tile kernel launch");
+    }
+    return Z4C_OK;
+}
+
+z4c_status need_device(const z4c_plan *P)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!P->device)
+        return fail(Z4C_ENODEV, "plan was created without a device");
+    return Z4C_OK;
+}
+
+z4c_status validate_stage(const z4c_plan *P, const double *u0_in, const double *u0_out,
+                          const double *u1, const double *u2, const double *matter,
+                          const z4c_rk_coeffs *c, double dt)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u0_in || !u0_out || !c)
+        return fail(Z4C_EINVAL, "u0_in, u0_out and coefficients must not be NULL");
+    if (u0_in == u0_out)
+        return fail(Z4C_EINVAL, "u0_out must not alias u0_in (neighbouring tiles read u0_in)");
+    if ((c->read_u1 || c->write_u1 || c->g2 != 0.0) && !u1)
+        return fail(Z4C_EINVAL, "u1 is NULL but the stage reads or writes it");
+    if (c->g3 != 0.0 && !u2)
+        return fail(Z4C_EINVAL, "u2 is NULL but g3 != 0");
+    if (u1 && (u1 == u0_in || u1 == u0_out))
+        return fail(Z4C_EINVAL, "u1 must not alias u0_in or u0_out");
+    if (u2 && u2 == u0_out)
+        return fail(Z4C_EINVAL, "u2 must not alias u0_out");
+    if (!aligned8(u0_in) || !aligned8(u0_out) || !aligned8(u1) || !aligned8(u2)
+        || !aligned8(matter))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (!std::isfinite(dt))
+        return fail(Z4C_EINVAL, "dt must be finite");
+    if (c->read_u1 < 0 || c->read_u1 > 1 || c->write_u1 < 0 || c->write_u1 > 1)
+        return fail(Z4C_EINVAL, "read_u1/write_u1 must be 0 or 1");
+    return Z4C_OK;
+}
+
+z4c_status enqueue_stage(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
+                         const double *u2, const double *matter, const z4c_rk_coeffs *c,
+                         double dt, hipStream_t s)
+{
+    StageArgs a = base_args(P);
+    a.u = u0_in;
+    a.matter = matter;
+    a.out = u0_out;
+    a.u1 = u1;
+    a.u2 = u2;
+    a.delta = c->delta;
+    a.eps_dt = c->eps * dt;
+    a.g1 = c->g1;
+    a.g2 = c->g2;
+    a.g3 = c->g3;
+    a.beta_dt = c->beta * dt;
+    a.read_u1 = c->read_u1;
+    a.write_u1 = c->write_u1;
+    a.use_u2 = c->g3 != 0.0;
+    a.u2_is_u0 = u2 == u0_in;
+    return run_groups(P, MODE_RK, P->params.arith, a, s);
+}
+
+z4c_status enqueue_ghost(z4c_plan *P, int policy, double *u, const double *frozen, hipStream_t s)
+{
+    if (policy == Z4C_GHOST_NONE)
+        return Z4C_OK;
+    GhostArgs g{};
+    g.blocks = P->blocks_d;
+    g.nblocks = P->nblocks;
+    g.ghost_start = P->ghost_start_d;
+    g.neighbours = P->nbr_d;
+    g.frozen = frozen;
+    g.u = u;
+    g.policy = policy;
+    const hipError_t e = launch_ghost(g, P->total_ghost, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "ghost kernel launch");
+    return Z4C_OK;
+}
+
+z4c_status validate_ghost(const z4c_plan *P, int policy, const double *u, const double *frozen)
+{
+    if (policy < 0 || policy > 3)
+        return fail(Z4C_EINVAL, "unknown ghost policy");
+    if (policy != Z4C_GHOST_NONE && !u)
+        return fail(Z4C_EINVAL, "u is NULL");
+    if (policy == Z4C_GHOST_FROZEN && !frozen)
+        return fail(Z4C_EINVAL, "frozen policy needs the frozen array");
+    if (policy == Z4C_GHOST_NEIGHBOUR && !P->has_nbr)
+        return fail(Z4C_EINVAL, "neighbour policy needs z4c_plan_set_neighbours first");
+    if (policy == Z4C_GHOST_PERIODIC && !P->periodic_ok)
+        return fail(Z4C_EINVAL, "periodic refresh needs nx, ny, nz >= ng for every block");
+    if (frozen && frozen == u)
+        return fail(Z4C_EINVAL, "frozen must not alias u");
+    if (!aligned8(u) || !aligned8(frozen))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    return Z4C_OK;
+}
+
+// Buffer schedule of a step: stage s reads regs[in_s]; every stage but the
+// last writes the first of {1, 2} it does not read; the last stage writes
+// regs[0] when it does not read u2 (= regs[0]), so that the step leaves the
+// new state where the old one was.
+z4c_status step_schedule(const z4c_step_desc *d, int in[8], int out[8], int *result)
+{
+    int cur = 0;
+    for (int s = 0; s < d->nstages; ++s) {
+        const bool last = s + 1 == d->nstages;
+        int o = cur == 1 ? 2 : 1;
+        if (last && d->table[s].g3 == 0.0)
+            o = 0;
+        in[s] = cur;
+        out[s] = o;
+        cur = o;
+    }
+    *result = cur;
+    return Z4C_OK;
+}
+
+z4c_status validate_step(const z4c_plan *P, const z4c_step_desc *d)
+{
+    if (!d)
+        return fail(Z4C_EINVAL, "step descriptor is NULL");
+    if (d->nstages < 1 || d->nstages > 8 || !d->table)
+        return fail(Z4C_EINVAL, "nstages must be in 1..8 with a coefficient table");
+    for (int r = 0; r < 4; ++r)
+        for (int q = r + 1; q < 4; ++q)
+            if (d->regs[r] && d->regs[r] == d->regs[q])
+                return fail(Z4C_EINVAL, "step registers must be distinct");
+    if (!d->regs[0] || !d->regs[1] || !d->regs[2])
+        return fail(Z4C_EINVAL, "regs[0..2] must not be NULL");
+    for (int s = 0; s < d->nstages; ++s) {
+        const z4c_rk_coeffs &c = d->table[s];
+        if ((c.read_u1 || c.write_u1 || c.g2 != 0.0) && !d->regs[3])
+            return fail(Z4C_EINVAL, "regs[3] (accumulator) is NULL but a stage uses it");
+    }
+    return validate_ghost(P, d->ghost_policy, d->regs[0], d->frozen);
+}
+
+z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStream_t s)
+{
+    int in[8], out[8], res;
+    z4c_status st = step_schedule(d, in, out, &res);
+    if (st != Z4C_OK)
+        return st;
+    for (int k = 0; k < d->nstages; ++k) {
+        const double *y = d->regs[0];
+        st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
+                           &d->table[k], d->dt, s);
+        if (st != Z4C_OK)
+            return st;
+        st = enqueue_ghost(P, d->ghost_policy, d->regs[out[k]], d->frozen, s);
+        if (st != Z4C_OK)
+            return st;
+    }
+    if (result)
+        *result = res;
+    return Z4C_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *z4c_strerror(z4c_status s)
+{
+    switch (s) {
+    case Z4C_OK: return "success";
+    case Z4C_EINVAL: return "invalid argument";
+    case Z4C_ENOGHOST: return "not enough ghost points for the stencil";
+    case Z4C_EALIGN: return "misaligned array";
+    case Z4C_EHIP: return "HIP runtime error";
+    case Z4C_ENOTSUP: return "not supported";
+    case Z4C_ENOMEM: return "device allocation failed";
+    case Z4C_ENODEV: return "plan has no device";
+    }
+    return "unknown status";
+}
+
+const char *z4c_last_error(void) { return g_last_error.c_str(); }
+
+z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, int nblocks,
+                           int flags, z4c_plan **out)
+{
+    if (!out)
+        return fail(Z4C_EINVAL, "out is NULL");
+    *out = nullptr;
+    z4c_status st = check_params(params);
+    if (st != Z4C_OK)
+        return st;
+    if (!blocks || nblocks < 1)
+        return fail(Z4C_EINVAL, "need at least one block");
+    for (int b = 0; b < nblocks; ++b) {
+        st = check_block(blocks[b], b, params->fd_order);
+        if (st != Z4C_OK)
+            return st;
+    }
+    z4c_plan *P = new z4c_plan();
+    P->params = *params;
+    P->device = !(flags & Z4C_PLAN_NO_DEVICE);
+    P->nblocks = nblocks;
+    P->blocks.assign(blocks, blocks + nblocks);
+    std::map<std::vector<int>, int> cls;
+    for (int b = 0; b < nblocks; ++b) {
+        const std::vector<int> key = {blocks[b].nx, blocks[b].ny, blocks[b].nz};
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            SizeClass c;
+            c.nx = blocks[b].nx;
+            c.ny = blocks[b].ny;
+            c.nz = blocks[b].nz;
+            c.launch = z4c_launch{8, 8, 8, 0};
+            c.blocks.push_back(b);
+            cls[key] = (int)P->classes.size();
+            P->classes.push_back(c);
+        } else {
+            P->classes[it->second].blocks.push_back(b);
+        }
+    }
+    // ghost-point and interior-point prefix sums
+    std::vector<long long> gs(nblocks + 1, 0), ps(nblocks + 1, 0);
+    for (int b = 0; b < nblocks; ++b) {
+        const z4c_block &B = blocks[b];
+        const long long ex = B.nx + 2LL * B.ng, ey = B.ny + 2LL * B.ng, ez = B.nz + 2LL * B.ng;
+        const long long interior = (long long)B.nx * B.ny * B.nz;
+        gs[b + 1] = gs[b] + ex * ey * ez - interior;
+        if (B.nx < B.ng || B.ny < B.ng || B.nz < B.ng)
+            P->periodic_ok = false;
+        ps[b + 1] = ps[b] + interior;
+    }
+    P->total_ghost = gs[nblocks];
+    P->total_pts = ps[nblocks];
+    if (P->device) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&P->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipMalloc(&P->blocks_d, sizeof(z4c_block) * nblocks);
+        if (e == hipSuccess)
+            e = hipMemcpy(P->blocks_d, blocks, sizeof(z4c_block) * nblocks, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMalloc(&P->ghost_start_d, sizeof(long long) * (nblocks + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(P->ghost_start_d, gs.data(), sizeof(long long) * (nblocks + 1),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMalloc(&P->pt_start_d, sizeof(long long) * (nblocks + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(P->pt_start_d, ps.data(), sizeof(long long) * (nblocks + 1),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMalloc(&P->count_d, sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            z4c_plan_destroy(P);
+            return hip_fail(e, "plan device set-up");
+        }
+    }
+    st = build_groups(P);
+    if (st == Z4C_OK)
+        st = upload_factors(P);
+    if (st != Z4C_OK) {
+        z4c_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return Z4C_OK;
+}
+
+z4c_status z4c_plan_destroy(z4c_plan *P)
+{
+    if (!P)
+        return Z4C_OK;
+    if (P->device) {
+        P->clear_graphs();
+        P->free_groups();
+        if (P->blocks_d)
+            (void)hipFree(P->blocks_d);
+        if (P->fac64_d)
+            (void)hipFree(P->fac64_d);
+        if (P->fac32_d)
+            (void)hipFree(P->fac32_d);
+        if (P->ghost_start_d)
+            (void)hipFree(P->ghost_start_d);
+        if (P->pt_start_d)
+            (void)hipFree(P->pt_start_d);
+        if (P->nbr_d)
+            (void)hipFree(P->nbr_d);
+        if (P->count_d)
+            (void)hipFree(P->count_d);
+        if (P->capture_stream)
+            (void)hipStreamDestroy(P->capture_stream);
+    }
+    delete P;
+    return Z4C_OK;
+}
+
+z4c_status z4c_plan_set_params(z4c_plan *P, const z4c_params *params)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    z4c_status st = check_params(params);
+    if (st != Z4C_OK)
+        return st;
+    for (int b = 0; b < P->nblocks; ++b) {
+        st = check_block(P->blocks[b], b, params->fd_order);
+        if (st != Z4C_OK)
+            return st;
+    }
+    P->params = *params;
+    if (P->device)
+        P->clear_graphs();
+    ++P->version;
+    return upload_factors(P);
+}
+
+z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
+{
+    if (!P || !nbr)
+        return fail(Z4C_EINVAL, "plan and neighbour table must not be NULL");
+    for (int b = 0; b < P->nblocks; ++b)
+        for (int d = 0; d < 27; ++d) {
+            const int n = nbr[b * 27 + d];
+            if (n < -1 || n >= P->nblocks)
+                return fail(Z4C_EINVAL, "neighbour index out of range");
+            if (n >= 0) {
+                const z4c_block &A = P->blocks[b], &B = P->blocks[n];
+                if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.ng != B.ng)
+                    return fail(Z4C_EINVAL, "neighbours must have equal nx, ny, nz, ng");
+                const int ox = d % 3 - 1, oy = (d / 3) % 3 - 1, oz = d / 9 - 1;
+                if ((ox && A.nx < A.ng) || (oy && A.ny < A.ng) || (oz && A.nz < A.ng))
+                    return fail(Z4C_EINVAL, "a neighbour copy needs n >= ng along its direction");
+            }
+        }
+    if (P->device) {
+        if (!P->nbr_d)
+            HIP_TRY(hipMalloc(&P->nbr_d, sizeof(int) * 27 * P->nblocks), "hipMalloc(neighbours)");
+        HIP_TRY(hipMemcpy(P->nbr_d, nbr, sizeof(int) * 27 * P->nblocks, hipMemcpyHostToDevice),
+                "hipMemcpy(neighbours)");
+        P->clear_graphs();
+    }
+    P->has_nbr = true;
+    ++P->version;
+    return Z4C_OK;
+}
+
+z4c_status z4c_plan_set_launch(z4c_plan *P, int nx, int ny, int nz, const z4c_launch *L)
+{
+    if (!P || !L)
+        return fail(Z4C_EINVAL, "plan and launch must not be NULL");
+    if (!stage_shape_supported(L->tile_x, L->tile_y, L->tile_z))
+        return fail(Z4C_ENOTSUP, "unsupported tile shape");
+    if (L->persistent < 0)
+        return fail(Z4C_EINVAL, "persistent must be >= 0");
+    bool any = false;
+    for (auto &c : P->classes)
+        if ((nx == 0 && ny == 0 && nz == 0) || (c.nx == nx && c.ny == ny && c.nz == nz)) {
+            c.launch = *L;
+            any = true;
+        }
+    if (!any)
+        return fail(Z4C_EINVAL, "no blocks of that size");
+    return build_groups(P);
+}
+
+z4c_status z4c_plan_get_launch(const z4c_plan *P, int nx, int ny, int nz, z4c_launch *L)
+{
+    if (!P || !L)
+        return fail(Z4C_EINVAL, "plan and launch must not be NULL");
+    for (const auto &c : P->classes)
+        if (c.nx == nx && c.ny == ny && c.nz == nz) {
+            *L = c.launch;
+            return Z4C_OK;
+        }
+    return fail(Z4C_EINVAL, "no blocks of that size");
+}
+
+long long z4c_plan_tiles(const z4c_plan *P) { return P ? P->total_tiles : -1; }
+
+z4c_status z4c_rhs(z4c_plan *P, const double *u, const double *matter, double *rhs, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u || !rhs)
+        return fail(Z4C_EINVAL, "u and rhs must not be NULL");
+    if (u == rhs || matter == rhs)
+        return fail(Z4C_EINVAL, "rhs must not alias u or matter");
+    if (!aligned8(u) || !aligned8(rhs) || !aligned8(matter))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    z4c_status st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    StageArgs a = base_args(P);
+    a.u = u;
+    a.matter = matter;
+    a.out = rhs;
+    return run_groups(P, MODE_RHS, P->params.arith, a, (hipStream_t)stream);
+}
+
+z4c_status z4c_rk_stage(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
+                        const double *u2, const double *matter, const z4c_rk_coeffs *c,
+                        double dt, void *stream)
+{
+    z4c_status st = validate_stage(P, u0_in, u0_out, u1, u2, matter, c, dt);
+    if (st != Z4C_OK)
+        return st;
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_stage(P, u0_in, u0_out, u1, u2, matter, c, dt, (hipStream_t)stream);
+}
+
+z4c_status z4c_constraints(z4c_plan *P, const double *u, const double *matter, double *cons,
+                           double *norms, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u || !norms)
+        return fail(Z4C_EINVAL, "u and norms must not be NULL");
+    if (cons == u || norms == u || (cons && cons == norms))
+        return fail(Z4C_EINVAL, "outputs must not alias u or each other");
+    if (!aligned8(u) || !aligned8(cons) || !aligned8(norms) || !aligned8(matter))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    z4c_status st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    StageArgs a = base_args(P);
+    a.u = u;
+    a.matter = matter;
+    a.out = cons;
+    a.partial = P->partial_d;
+    hipStream_t s = (hipStream_t)stream;
+    st = run_groups(P, MODE_CONS, Z4C_ARITH_FP64, a, s);
+    if (st != Z4C_OK)
+        return st;
+    const hipError_t e = launch_norm_reduce(P->blocks_d, P->nblocks, P->tile_start_d,
+                                            P->tile_count_d, P->partial_d, norms, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "norm reduction launch");
+    return Z4C_OK;
+}
+
+z4c_status z4c_ghost_fill(z4c_plan *P, int policy, double *u, const double *frozen, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    z4c_status st = validate_ghost(P, policy, u, frozen);
+    if (st != Z4C_OK)
+        return st;
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_ghost(P, policy, u, frozen, (hipStream_t)stream);
+}
+
+z4c_status z4c_step(z4c_plan *P, const z4c_step_desc *d, int *result, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    z4c_status st = validate_step(P, d);
+    if (st != Z4C_OK)
+        return st;
+    int in[8], out[8], res;
+    st = step_schedule(d, in, out, &res);
+    if (st != Z4C_OK)
+        return st;
+    for (int k = 0; k < d->nstages; ++k) {
+        st = validate_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], d->regs[0], d->matter,
+                            &d->table[k], d->dt);
+        if (st != Z4C_OK)
+            return st;
+    }
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_step(P, d, result, (hipStream_t)stream);
+}
+
+z4c_status z4c_step_graph(z4c_plan *P, const z4c_step_desc *d, int *result, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    z4c_status st = validate_step(P, d);
+    if (st != Z4C_OK)
+        return st;
+    {
+        int in0[8], out0[8], r0;
+        st = step_schedule(d, in0, out0, &r0);
+        if (st != Z4C_OK)
+            return st;
+        for (int k = 0; k < d->nstages; ++k) {
+            st = validate_stage(P, d->regs[in0[k]], d->regs[out0[k]], d->regs[3], d->regs[0],
+                                d->matter, &d->table[k], d->dt);
+            if (st != Z4C_OK)
+                return st;
+        }
+    }
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    StepKey key;
+    std::memset(&key, 0, sizeof key);
+    for (int r = 0; r < 4; ++r)
+        key.regs[r] = d->regs[r];
+    key.matter = d->matter;
+    key.frozen = d->frozen;
+    key.dt = d->dt;
+    key.nstages = d->nstages;
+    key.ghost_policy = d->ghost_policy;
+    for (int s = 0; s < d->nstages; ++s)
+        key.table[s] = d->table[s];
+    key.version = P->version;
+    for (const auto &g : P->graphs)
+        if (g.key == key) {
+            HIP_TRY(hipGraphLaunch(g.exec, (hipStream_t)stream), "hipGraphLaunch");
+            if (result)
+                *result = g.result;
+            return Z4C_OK;
+        }
+    int in[8], out[8], res;
+    st = step_schedule(d, in, out, &res);
+    if (st != Z4C_OK)
+        return st;
+    for (int k = 0; k < d->nstages; ++k) {
+        st = validate_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], d->regs[0], d->matter,
+                            &d->table[k], d->dt);
+        if (st != Z4C_OK)
+            return st;
+    }
+    hipStream_t cs = P->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    st = enqueue_step(P, d, nullptr, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (st != Z4C_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ee != hipSuccess)
+        return hip_fail(ee, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess)
+        return hip_fail(ei, "hipGraphInstantiate");
+    if (P->graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(P->graphs.front().exec);
+        P->graphs.erase(P->graphs.begin());
+    }
+    P->graphs.push_back(GraphEntry{key, exec, res});
+    HIP_TRY(hipGraphLaunch(exec, (hipStream_t)stream), "hipGraphLaunch");
+    if (result)
+        *result = res;
+    return Z4C_OK;
+}
+
+z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, double *u1,
+                             const double *matter, int reps, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u0 || !u0_out || !u1 || u0 == u0_out || u1 == u0 || u1 == u0_out)
+        return fail(Z4C_EINVAL, "autotune needs three distinct state buffers");
+    if (reps < 1)
+        return fail(Z4C_EINVAL, "reps must be >= 1");
+    z4c_status st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    const z4c_rk_coeffs c{0.0, 1.0 / 3.0, 0.0, 0.0, 1.0, 0.5, 1, 1};
+    static const int shapes[][3] = {{8, 8, 8}, {8, 8, 4}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    const std::vector<SizeClass> saved = P->classes;
+    std::vector<z4c_launch> best(P->classes.size());
+    for (size_t ci = 0; ci < saved.size(); ++ci) {
+        float best_ms = 1e30f;
+        for (const auto &sh : shapes) {
+            for (int pers : {0, 1}) {
+                z4c_launch L{sh[0], sh[1], sh[2], pers ? 2 * P->num_cus : 0};
+                // a plan view holding only this size class
+                P->classes.assign(1, saved[ci]);
+                P->classes[0].launch = L;
+                st = build_groups(P);
+                if (st != Z4C_OK)
+                    break;
+                st = enqueue_stage(P, u0, u0_out, u1, u0, matter, &c, 1e-3, s);   // warm-up
+                if (st != Z4C_OK)
+                    break;
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps && st == Z4C_OK; ++r)
+                    st = enqueue_stage(P, u0, u0_out, u1, u0, matter, &c, 1e-3, s);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (st == Z4C_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best[ci] = L;
+                }
+            }
+            if (st != Z4C_OK)
+                break;
+        }
+        if (st != Z4C_OK)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->classes = saved;
+    if (st == Z4C_OK)
+        for (size_t ci = 0; ci < saved.size(); ++ci)
+            P->classes[ci].launch = best[ci];
+    const z4c_status st2 = build_groups(P);
+    return st != Z4C_OK ? st : st2;
+}
+
+z4c_status z4c_check_finite(z4c_plan *P, const double *u, long long *count, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u || !count)
+        return fail(Z4C_EINVAL, "u and count must not be NULL");
+    z4c_status st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_zero_u64(P->count_d, s), "zero kernel");
+    HIP_TRY(launch_finite_count(P->blocks_d, P->nblocks, P->pt_start_d, P->total_pts, u, P->count_d,
+                                s),
+            "finite-count kernel");
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, P->count_d, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    *count = (long long)h;
+    return Z4C_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernel and host translation units of
+// libz4c.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "z4c.h"
+
+namespace z4c {
+
+// State field indices (order fixed by the ABI).
+enum Field : int {
+    CHI = 0, GXX = 1, GXY, GXZ, GYY, GYZ, GZZ, KHAT = 7,
+    AXX = 8, AXY, AXZ, AYY, AYZ, AZZ, THETA = 14,
+    GAMX = 15, GAMY, GAMZ, ALPHA = 18, BETAX = 19, BETAY, BETAZ, NFIELD = 22
+};
+enum MatterField : int { M_RHO = 0, M_SX, M_SY, M_SZ, M_SXX, M_SXY, M_SXZ, M_SYY, M_SYZ, M_SZZ,
+                         NMATTER = 10 };
+enum ConsField : int { C_H = 0, C_MX, C_MY, C_MZ, C_THETA, C_ZX, C_ZY, C_ZZ, NCONS = 8 };
+
+// What a tile kernel produces.
+enum Mode : int { MODE_RHS = 0, MODE_RK = 1, MODE_CONS = 2 };
+
+// One work item of a tile kernel: block index and interior origin of the tile.
+struct Tile {
+    int block, i0, j0, k0;
+};
+
+struct StageArgs {
+    const z4c_block *blocks;
+    const double *fac64;     // per block: 12 stencil scale factors (see block_factors)
+    const float *fac32;      // the same factors rounded to float
+    const Tile *tiles;
+    int ntiles;
+    int persistent;          // 0: one workgroup per tile
+    long long tile_base;     // global index of tiles[0] (norm partial sums)
+    const double *u;         // input state (u0 for a stage)
+    const double *matter;    // nullptr = vacuum
+    double *out;             // rhs, u0_out, or constraint fields (may be nullptr for CONS)
+    double *u1;
+    const double *u2;
+    double *partial;         // CONS: per-tile sums, [tile][16]
+    // Runge-Kutta stage
+    double delta, eps_dt, g1, g2, g3, beta_dt;
+    int read_u1, write_u1, use_u2, u2_is_u0;
+    // scheme
+    double ko_sigma, kappa1, kappa2, eta, chi_floor, alpha_floor;
+    int lapse, shift, advect_gauge;
+};
+
+struct GhostArgs {
+    const z4c_block *blocks;
+    int nblocks;
+    const long long *ghost_start;   // nblocks + 1 prefix sums of ghost points
+    const int *neighbours;          // nblocks*27 or nullptr
+    const double *frozen;
+    double *u;
+    int policy;
+};
+
+// Stencil scale factors of one block, in order d1[3], d2[3], mix[3] (xy, xz,
+// yz), ko[3]:  d1 = 1/(c1 h), d2 = 1/(c2 h^2), mix = d1_a d1_b,
+// ko = (-1)^(r+1) sigma / (2^(2r) h), with (c1, c2) = (12, 12) for order 4 and
+// (60, 180) for order 6, r = order/2 + 1.
+void block_factors(const z4c_block &b, int fd_order, double sigma, double out[12]);
+
+// Launch entry points implemented in z4c_kernels.hip.
+hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz,
+                        const StageArgs &a, hipStream_t s);
+bool stage_shape_supported(int tx, int ty, int tz);
+hipError_t launch_ghost(const GhostArgs &g, long long total_ghost, hipStream_t s);
+hipError_t launch_norm_reduce(const z4c_block *blocks, int nblocks, const long long *tile_start,
+                              const int *tile_count, const double *partial, double *norms,
+                              hipStream_t s);
+hipError_t launch_finite_count(const z4c_block *blocks, int nblocks, const long long *pt_start,
+                               long long total_pts, const double *u,
+                               unsigned long long *count, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+
+}  // namespace z4c

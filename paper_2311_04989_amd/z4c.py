@@ -1,0 +1,262 @@
+"""Python binding of libz4c.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of the C-ABI library; this module
+converts Python objects to the C structures of ``include/z4c.h`` and device
+addresses (integers, e.g. ``torch.Tensor.data_ptr()``), raises on error
+statuses, and fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libz4c.so")
+
+OK, EINVAL, ENOGHOST, EALIGN, EHIP, ENOTSUP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+LAPSE_1PLUSLOG, LAPSE_HARMONIC, LAPSE_FROZEN = 0, 1, 2
+SHIFT_GAMMADRIVER, SHIFT_FROZEN = 0, 1
+ARITH_FP64, ARITH_FP32 = 0, 1
+GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
+PLAN_NO_DEVICE = 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("fd_order", ctypes.c_int), ("ko_sigma", ctypes.c_double),
+                ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double),
+                ("eta", ctypes.c_double), ("lapse", ctypes.c_int), ("shift", ctypes.c_int),
+                ("advect_gauge", ctypes.c_int), ("chi_floor", ctypes.c_double),
+                ("alpha_floor", ctypes.c_double), ("arith", ctypes.c_int)]
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_longlong), ("moffset", ctypes.c_longlong),
+                ("coffset", ctypes.c_longlong), ("field_stride", ctypes.c_longlong),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("ng", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("dz", ctypes.c_double)]
+
+
+class RKCoeffs(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("eps", ctypes.c_double), ("g1", ctypes.c_double),
+                ("g2", ctypes.c_double), ("g3", ctypes.c_double), ("beta", ctypes.c_double),
+                ("read_u1", ctypes.c_int), ("write_u1", ctypes.c_int)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("tile_z", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
+
+
+class StepDesc(ctypes.Structure):
+    _fields_ = [("regs", ctypes.c_void_p * 4), ("matter", ctypes.c_void_p),
+                ("table", ctypes.POINTER(RKCoeffs)), ("nstages", ctypes.c_int),
+                ("dt", ctypes.c_double), ("ghost_policy", ctypes.c_int),
+                ("frozen", ctypes.c_void_p)]
+
+
+# Classic RK4 in the library's three-register stage form.
+RK4 = [(1.0, 1.0 / 6.0, 0.0, 0.0, 1.0, 0.5, 0, 1),
+       (0.0, 1.0 / 3.0, 0.0, 0.0, 1.0, 0.5, 1, 1),
+       (0.0, 1.0 / 3.0, 0.0, 0.0, 1.0, 1.0, 1, 1),
+       (0.0, 1.0 / 6.0, 0.0, 1.0, 0.0, 0.0, 1, 0)]
+# SSPRK(3,3) (Shu-Osher) in the same form; the accumulator is unused.
+SSPRK3 = [(0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0, 0),
+          (0.0, 0.0, 0.25, 0.0, 0.75, 0.25, 0, 0),
+          (0.0, 0.0, 2.0 / 3.0, 0.0, 1.0 / 3.0, 2.0 / 3.0, 0, 0)]
+
+
+class Z4cError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"z4c status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIBPATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int
+        L.z4c_plan_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Block), ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(vp)]
+        L.z4c_plan_destroy.argtypes = [vp]
+        L.z4c_plan_set_params.argtypes = [vp, ctypes.POINTER(Params)]
+        L.z4c_plan_set_neighbours.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.z4c_plan_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(Launch)]
+        L.z4c_plan_get_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(Launch)]
+        L.z4c_rhs.argtypes = [vp, vp, vp, vp, vp]
+        L.z4c_rk_stage.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
+                                   ctypes.c_double, vp]
+        L.z4c_constraints.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.z4c_ghost_fill.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.z4c_step.argtypes = [vp, ctypes.POINTER(StepDesc), ctypes.POINTER(ctypes.c_int), vp]
+        L.z4c_step_graph.argtypes = [vp, ctypes.POINTER(StepDesc), ctypes.POINTER(ctypes.c_int),
+                                     vp]
+        L.z4c_plan_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
+        L.z4c_check_finite.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]
+        L.z4c_strerror.argtypes = [st]
+        L.z4c_strerror.restype = ctypes.c_char_p
+        L.z4c_last_error.restype = ctypes.c_char_p
+        L.z4c_plan_tiles.argtypes = [vp]
+        L.z4c_plan_tiles.restype = ctypes.c_longlong
+        for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params",
+                     "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
+                     "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill",
+                     "z4c_step", "z4c_step_graph", "z4c_plan_autotune", "z4c_check_finite"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise Z4cError(status, lib().z4c_last_error().decode())
+
+
+def make_params(p, arith: int = ARITH_FP64) -> Params:
+    """C parameters from any object with the scheme-parameter attributes."""
+    return Params(int(p.fd_order), float(p.ko_sigma), float(p.kappa1), float(p.kappa2),
+                  float(p.eta), int(p.lapse), int(p.shift), int(p.advect_gauge),
+                  float(p.chi_floor), float(p.alpha_floor), int(arith))
+
+
+def make_blocks(table: np.ndarray):
+    """C block array from a structured numpy array with the z4c_block fields."""
+    arr = (Block * len(table))()
+    for i, r in enumerate(table):
+        arr[i] = Block(int(r["offset"]), int(r["moffset"]), int(r["coffset"]),
+                       int(r["field_stride"]), int(r["nx"]), int(r["ny"]), int(r["nz"]),
+                       int(r["ng"]), float(r["dx"]), float(r["dy"]), float(r["dz"]))
+    return arr
+
+
+def _coeffs(c) -> RKCoeffs:
+    if isinstance(c, RKCoeffs):
+        return c
+    if isinstance(c, dict):
+        return RKCoeffs(c["delta"], c["eps"], c["g1"], c["g2"], c["g3"], c["beta"],
+                        int(c["read_u1"]), int(c["write_u1"]))
+    return RKCoeffs(*c)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return 0
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x)
+
+
+class Plan:
+    """A validated set of MeshBlocks with device tables (z4c_plan)."""
+
+    def __init__(self, params: Params, blocks, flags: int = 0):
+        self._h = ctypes.c_void_p()
+        self.nblocks = len(blocks)
+        _check(lib().z4c_plan_create(ctypes.byref(params), blocks, self.nblocks, flags,
+                                     ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().z4c_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tiles(self) -> int:
+        return int(lib().z4c_plan_tiles(self._h))
+
+    def set_params(self, params: Params):
+        _check(lib().z4c_plan_set_params(self._h, ctypes.byref(params)))
+
+    def set_neighbours(self, table: np.ndarray):
+        t = np.ascontiguousarray(table, dtype=np.int32).reshape(-1)
+        _check(lib().z4c_plan_set_neighbours(self._h, t.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int))))
+
+    def set_launch(self, nx, ny, nz, tile=(8, 8, 8), persistent=0):
+        L = Launch(tile[0], tile[1], tile[2], persistent)
+        _check(lib().z4c_plan_set_launch(self._h, nx, ny, nz, ctypes.byref(L)))
+
+    def get_launch(self, nx, ny, nz):
+        L = Launch()
+        _check(lib().z4c_plan_get_launch(self._h, nx, ny, nz, ctypes.byref(L)))
+        return (L.tile_x, L.tile_y, L.tile_z), L.persistent
+
+    def rhs(self, u, matter, out, stream=None):
+        _check(lib().z4c_rhs(self._h, _ptr(u), _ptr(matter), _ptr(out), _stream(stream)))
+
+    def rk_stage(self, u0_in, u0_out, u1, u2, matter, coeffs, dt, stream=None):
+        c = _coeffs(coeffs)
+        _check(lib().z4c_rk_stage(self._h, _ptr(u0_in), _ptr(u0_out), _ptr(u1), _ptr(u2),
+                                  _ptr(matter), ctypes.byref(c), float(dt), _stream(stream)))
+
+    def constraints(self, u, matter, cons, norms, stream=None):
+        _check(lib().z4c_constraints(self._h, _ptr(u), _ptr(matter), _ptr(cons), _ptr(norms),
+                                     _stream(stream)))
+
+    def ghost_fill(self, policy, u, frozen=None, stream=None):
+        _check(lib().z4c_ghost_fill(self._h, int(policy), _ptr(u), _ptr(frozen),
+                                    _stream(stream)))
+
+    def _desc(self, regs, matter, table, dt, ghost, frozen):
+        tab = (RKCoeffs * len(table))(*[_coeffs(c) for c in table])
+        d = StepDesc()
+        for r in range(4):
+            d.regs[r] = _ptr(regs[r]) if r < len(regs) else 0
+        d.matter = _ptr(matter)
+        d.table = tab
+        d.nstages = len(table)
+        d.dt = float(dt)
+        d.ghost_policy = int(ghost)
+        d.frozen = _ptr(frozen)
+        return d, tab
+
+    def step(self, regs, matter, table, dt, ghost, frozen=None, stream=None, graph=False) -> int:
+        """One Runge-Kutta step; returns the index of the register holding the
+        new state."""
+        d, tab = self._desc(regs, matter, table, dt, ghost, frozen)
+        res = ctypes.c_int(-1)
+        fn = lib().z4c_step_graph if graph else lib().z4c_step
+        _check(fn(self._h, ctypes.byref(d), ctypes.byref(res), _stream(stream)))
+        return res.value
+
+    def autotune(self, u0, u0_out, u1, matter, reps=3, stream=None):
+        _check(lib().z4c_plan_autotune(self._h, _ptr(u0), _ptr(u0_out), _ptr(u1), _ptr(matter),
+                                       int(reps), _stream(stream)))
+
+    def check_finite(self, u, stream=None) -> int:
+        n = ctypes.c_longlong(0)
+        _check(lib().z4c_check_finite(self._h, _ptr(u), ctypes.byref(n), _stream(stream)))
+        return n.value
+
+
+def plan_for(batch, arith: int = ARITH_FP64, flags: int = 0) -> Plan:
+    """Plan for a workload batch (its block table, parameters, neighbours)."""
+    p = Plan(make_params(batch.params, arith), make_blocks(batch.block_table()), flags)
+    if batch.neighbours is not None:
+        p.set_neighbours(batch.neighbours)
+    return p

@@ -1,0 +1,58 @@
+"""Parity metric between the GPU path and the oracle (test helper).
+
+Per field f and interior point p, with the extended-precision oracle o as
+reference (the same oracle source computed in x87 extended precision):
+
+    e(p) = |g(p) - o(p)| / max(|o(p)|, tau_f),   tau_f = 1e-3 * max_p |o_f|
+
+The gate is  max_p e <= tol_f = max(1e-12, 8 * max_p e_oracle),  where
+e_oracle is the same error of the FP64 oracle against o.  On fields whose
+value is a near-cancellation of much larger terms (Theta on constraint-
+satisfying data, At on the star metric) the FP64 oracle itself is only
+good to a few 1e-12; there the GPU must be within 8x of the oracle's own
+rounding error, elsewhere within 1e-12.  Fields that are exactly zero in
+the oracle must be exactly zero on the GPU.
+"""
+import numpy as np
+
+from paper_2311_04989_amd import workloads as W
+
+
+def compare(batch, gpu, o64, o80, nfields=W.NF, base=None, blocks=None, names=None,
+            rel_floor=1e-3, gate=1e-12):
+    names = names or (W.FIELDS if nfields == W.NF else W.CONSTRAINTS)
+    blocks = range(len(batch.blocks)) if blocks is None else blocks
+    rows = []
+    for f in range(nfields):
+        g = np.concatenate([batch.interior(gpu, b, f, nfields).ravel() for b in blocks])
+        c = np.concatenate([batch.interior(o64, b, f, nfields).ravel() for b in blocks])
+        o = np.concatenate([batch.interior(o80, b, f, nfields).ravel() for b in blocks])
+        if base is not None:
+            z = np.concatenate([batch.interior(base, b, f, nfields).ravel() for b in blocks])
+            g, c, o = g - z, c - z, o - z
+        m = np.abs(o).max()
+        if m == 0.0:
+            rows.append((names[f], float(np.abs(g).max()), 0.0, 0.0, m))
+            continue
+        tau = rel_floor * m
+        den = np.maximum(np.abs(o), tau)
+        eg = float((np.abs(g - o) / den).max())
+        ec = float((np.abs(c - o) / den).max())
+        rows.append((names[f], eg, ec, max(gate, 8.0 * ec), m))
+    return rows
+
+
+def assert_parity(rows, label=""):
+    bad = []
+    for name, eg, ec, tol, m in rows:
+        if m == 0.0:
+            if eg != 0.0:
+                bad.append(f"{name}: oracle exactly 0, GPU max |g| = {eg:.3e}")
+        elif not eg <= tol:
+            bad.append(f"{name}: e_gpu={eg:.3e} > tol={tol:.3e} (e_fp64_oracle={ec:.3e})")
+    assert not bad, label + "\n" + "\n".join(bad)
+
+
+def report(rows):
+    return "\n".join(f"  {n:6s} e_gpu={eg:.2e} e_oracle64={ec:.2e} tol={tol:.2e} max|o|={m:.2e}"
+                     for n, eg, ec, tol, m in rows)
