@@ -354,8 +354,8 @@ z4c_status validate_stage(const z4c_plan *P, const double *u0_in, const double *
         return fail(Z4C_EINVAL, "u2 is NULL but g3 != 0");
     if (u1 && (u1 == u0_in || u1 == u0_out))
         return fail(Z4C_EINVAL, "u1 must not alias u0_in or u0_out");
-    if (u2 && u2 == u0_out)
-        return fail(Z4C_EINVAL, "u2 must not alias u0_out");
+    if (c->g3 != 0.0 && u2 == u0_out)
+        return fail(Z4C_EINVAL, "u2 must not alias u0_out when the stage reads it");
     if (!aligned8(u0_in) || !aligned8(u0_out) || !aligned8(u1) || !aligned8(u2)
         || !aligned8(matter))
         return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
@@ -386,6 +386,8 @@ z4c_status enqueue_stage(z4c_plan *P, const double *u0_in, double *u0_out, doubl
     a.write_u1 = c->write_u1;
     a.use_u2 = c->g3 != 0.0;
     a.u2_is_u0 = u2 == u0_in;
+    if (!a.use_u2)
+        a.u2 = nullptr;
     return run_groups(P, MODE_RK, P->params.arith, a, s);
 }
 

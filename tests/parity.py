@@ -12,6 +12,14 @@ satisfying data, At on the star metric) the FP64 oracle itself is only
 good to a few 1e-12; there the GPU must be within 8x of the oracle's own
 rounding error, elsewhere within 1e-12.  Fields that are exactly zero in
 the oracle must be exactly zero on the GPU.
+
+State outputs (a stage or a step) are compared through their increments
+(state minus a base state), since states near 1 would make the comparison
+vacuous.  Every implementation rounds the stored state to double, and a
+different but correctly rounded sequence (a fused multiply-add) can land
+one or two units in the last place (ulp) away; so for increments the
+error first has 4 ulp of the stored state value subtracted:
+    e(p) = max(|g - o| - 4 ulp(|x(p)|), 0) / max(|o|, tau_f).
 """
 import numpy as np
 
@@ -27,8 +35,10 @@ def compare(batch, gpu, o64, o80, nfields=W.NF, base=None, blocks=None, names=No
         g = np.concatenate([batch.interior(gpu, b, f, nfields).ravel() for b in blocks])
         c = np.concatenate([batch.interior(o64, b, f, nfields).ravel() for b in blocks])
         o = np.concatenate([batch.interior(o80, b, f, nfields).ravel() for b in blocks])
+        allow = 0.0
         if base is not None:
             z = np.concatenate([batch.interior(base, b, f, nfields).ravel() for b in blocks])
+            allow = 4.0 * np.spacing(np.abs(o))
             g, c, o = g - z, c - z, o - z
         m = np.abs(o).max()
         if m == 0.0:
@@ -36,8 +46,8 @@ def compare(batch, gpu, o64, o80, nfields=W.NF, base=None, blocks=None, names=No
             continue
         tau = rel_floor * m
         den = np.maximum(np.abs(o), tau)
-        eg = float((np.abs(g - o) / den).max())
-        ec = float((np.abs(c - o) / den).max())
+        eg = float((np.maximum(np.abs(g - o) - allow, 0.0) / den).max())
+        ec = float((np.maximum(np.abs(c - o) - allow, 0.0) / den).max())
         rows.append((names[f], eg, ec, max(gate, 8.0 * ec), m))
     return rows
 
