@@ -5,8 +5,10 @@ Workload (a "step"): one classic RK4 step of an uneven MeshBlock level set,
 1,024 blocks of 8^3/16^3/24^3/32^3 interior points (410/307/205/102) with 4
 ghost points, 6th-order finite differences, Kreiss-Oliger 0.5, 1+log lapse,
 Gamma-driver shift, flat space + U(-1e-8, 1e-8) noise; each of the 4 stages
-is one fused RHS + Runge-Kutta launch followed by a periodic ghost refresh,
-the whole step captured in one HIP graph and replayed.
+is one fused RHS + Runge-Kutta launch,
+the whole step captured in one HIP graph and replayed.  Ghost points are
+read through the periodic rule inside the stage kernels (no separate
+refresh pass; the stored ghosts are not rewritten).
 
 Metric: interior grid-point stage updates per second (one point through one
 RHS evaluation and Runge-Kutta combination), FP64.  The same step with
@@ -83,6 +85,7 @@ def main():
         plan = Z.plan_for(bt, arith)
         regs = [y0.clone(), y0.clone(), y0.clone(), torch.zeros_like(y0)]
         plan.ghost_fill(Z.GHOST_PERIODIC, regs[0], stream=stream)
+        plan.set_halo(Z.GHOST_PERIODIC)   # stage launches outside the step read the same way
         if not args.no_autotune:
             plan.autotune(regs[0], regs[1], regs[3], None, reps=3, stream=stream)
         launches = {s: plan.get_launch(s, s, s) for s in (8, 16, 24, 32)}
@@ -90,14 +93,16 @@ def main():
         log(f"[bench] {label}: launch shapes {launches}")
         # warm-up (captures the graph on the first call)
         for _ in range(args.warmup):
-            r = plan.step(regs, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream)
+            r = plan.step(regs, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream,
+                          flags=Z.STEP_NO_FINAL_FILL)
             assert r == 0
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(args.steps):
-            plan.step(regs, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream)
+            plan.step(regs, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream,
+                      flags=Z.STEP_NO_FINAL_FILL)
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
@@ -105,9 +110,8 @@ def main():
         # stage-kernel durations: the same step eager, an event pair around
         # each fused stage launch on the launch stream
         stage_ms = np.zeros(nstages)
-        ghost_ms = 0.0
         reps = max(3, args.steps // 2)
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nstages + 1)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nstages)]
         sched_in, sched_out = [0, 1, 2, 1], [1, 2, 1, 0]
         tab = Z.RK4
         for _ in range(reps):
@@ -116,20 +120,23 @@ def main():
                 plan.rk_stage(regs[sched_in[s]], regs[sched_out[s]], regs[3], regs[0], None,
                               tab[s], bt.dt, stream=stream)
                 evs[2 * s + 1].record(stream)
-                plan.ghost_fill(Z.GHOST_PERIODIC, regs[sched_out[s]], stream=stream)
-            evs[-1].record(stream)
             torch.cuda.synchronize()
             for s in range(nstages):
                 stage_ms[s] += evs[2 * s].elapsed_time(evs[2 * s + 1])
-                ghost_ms += evs[2 * s + 1].elapsed_time(evs[2 * s + 2] if s + 1 < nstages
-                                                        else evs[-1])
         stage_ms /= reps
-        ghost_ms /= reps * nstages
+        # a stored-ghost refresh, timed alone for reference (not part of the step)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.ghost_fill(Z.GHOST_PERIODIC, regs[1], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ghost_ms = e0.elapsed_time(e1)
         nonfinite = plan.check_finite(regs[0], stream=stream)
         results[label] = dict(ms=ms, stage_ms=stage_ms, ghost_ms=ghost_ms, launches=launches,
                               nonfinite=nonfinite)
         log(f"[bench] {label}: stage kernels {np.round(stage_ms, 3).tolist()} ms, "
-            f"ghost refresh {ghost_ms:.3f} ms, non-finite values {nonfinite}")
+            f"(a separate ghost refresh would cost {ghost_ms:.3f} ms), non-finite values "
+            f"{nonfinite}")
         del regs
         plan.close()
 
@@ -154,8 +161,8 @@ def main():
         "config": {
             "workload": "uneven AMR level set: 1024 MeshBlocks 8^3/16^3/24^3/32^3 "
                         "(410/307/205/102) + 4 ghosts, 6th-order FD, KO 0.5, flat space + "
-                        "1e-8 noise, one RK4 step = 4 fused RHS+RK stages + periodic ghost "
-                        "refresh in one HIP graph",
+                        "1e-8 noise, one RK4 step = 4 fused RHS+RK stages reading ghosts "
+                        "through the periodic rule, in one HIP graph",
             "interior_points": n_int,
             "stored_points": bt.nstored,
             "stages_per_step": nstages,
@@ -163,7 +170,7 @@ def main():
         },
         "zone_cycles_per_s": n_int / (r64["ms"] * 1e-3),
         "stage_kernel_ms": r64["stage_ms"].round(4).tolist(),
-        "ghost_refresh_ms": round(r64["ghost_ms"], 4),
+        "separate_ghost_refresh_ms": round(r64["ghost_ms"], 4),
         "roofline": {
             "bound": "hbm",
             "achieved": achieved_gbs,

@@ -138,15 +138,30 @@ z4c_status z4c_plan_set_params(z4c_plan *plan, const z4c_params *params);
 z4c_status z4c_plan_set_neighbours(z4c_plan *plan, const int *neighbours);
 
 /* Launch shape for the blocks of one size class (nx, ny, nz) (0 = all).
- * tile_x/y/z: interior points per workgroup, one thread per point
- * (supported: 8x8x8, 8x8x4); persistent: 0 = one workgroup per tile,
- * otherwise that many workgroups each take a contiguous run of tiles. */
+ * tile_x/y/z: interior points per workgroup, one thread per point;
+ * persistent: 0 = one workgroup per tile, otherwise that many workgroups
+ * each take a contiguous run of tiles; waves: occupancy the kernel variant
+ * is compiled for, in waves per SIMD (0 = 2; its register budget is
+ * 512/waves per lane).  Supported for order 6: 8x8x8 with waves 2, 3, 4 and
+ * 8x8x4 with waves 2, 4; for order 4: 8x8x8 and 8x8x4 with waves 2. */
 typedef struct {
     int tile_x, tile_y, tile_z;
     int persistent;
+    int waves;
 } z4c_launch;
 z4c_status z4c_plan_set_launch(z4c_plan *plan, int nx, int ny, int nz, const z4c_launch *launch);
 z4c_status z4c_plan_get_launch(const z4c_plan *plan, int nx, int ny, int nz, z4c_launch *launch);
+
+/* How z4c_rhs, z4c_rk_stage and z4c_constraints obtain the ghost points of
+ * their input: Z4C_GHOST_NONE (default) reads the stored ghost values;
+ * PERIODIC, NEIGHBOUR (table from z4c_plan_set_neighbours; -1 entries read
+ * `frozen`) and FROZEN read, for every ghost point, the value a
+ * z4c_ghost_fill with that policy would store there — straight from the
+ * source, so no refresh pass is needed and the stored ghosts are ignored.
+ * Rule-based reads need offset + 22*field_stride < 2^32 for every block
+ * (Z4C_ENOTSUP otherwise).  `frozen` (device, state layout) must stay valid
+ * while calls that use it are pending. */
+z4c_status z4c_plan_set_halo(z4c_plan *plan, int policy, const double *frozen);
 
 /* d_t u at every interior point (dissipation included) -> rhs (state layout).
  * u, rhs: device; rhs must not alias u. */
@@ -170,19 +185,27 @@ z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter
                            double *cons, double *norms, void *stream);
 
 /* Refresh the ghost points of `u` (device): periodic, neighbour (table set
- * with z4c_plan_set_neighbours; -1 entries take `frozen`), or frozen
- * (`frozen` device array in the state layout). */
+ * with z4c_plan_set_neighbours; -1 entries take `frozen`, or keep their
+ * stored value when `frozen` is NULL), or frozen (`frozen` device array in
+ * the state layout). */
 z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *frozen,
                           void *stream);
 
-/* One full Runge-Kutta step: for each stage s, z4c_rk_stage then
- * z4c_ghost_fill(ghost_policy) on the stage output.  Buffers regs[0..3]:
+/* One full Runge-Kutta step of nstages fused stages.  With a ghost policy
+ * other than NONE every stage reads the ghost points of its input through
+ * that policy (as z4c_plan_set_halo describes), so no refresh pass runs
+ * between stages; the ghosts of the final state are then refreshed once
+ * (unless Z4C_STEP_NO_FINAL_FILL).  Z4C_STEP_STORED_GHOSTS instead refreshes
+ * the stored ghosts of every stage output with z4c_ghost_fill and lets the
+ * stages read them; both give bitwise the same interior.  Buffers regs[0..3]:
  * regs[0] holds y_n on entry; regs[1], regs[2] are stage ping-pong buffers;
  * regs[3] is the accumulator.  Stage s reads regs[in_s] (in_0 = 0) and
  * writes regs[out_s]: the one of {1, 2} it does not read, except that the
  * last stage writes regs[0] when its g3 == 0 (it does not read y_n).  The
  * final state's index is returned in *result (0 for classic RK4, so the
  * step can be repeated with the same registers). */
+#define Z4C_STEP_STORED_GHOSTS 1   /* refresh stored ghosts after every stage    */
+#define Z4C_STEP_NO_FINAL_FILL 2   /* do not refresh the final state's ghosts     */
 typedef struct {
     double *regs[4];
     const double *matter;
@@ -191,6 +214,7 @@ typedef struct {
     double dt;
     int ghost_policy;
     const double *frozen;
+    int flags;                    /* Z4C_STEP_* */
 } z4c_step_desc;
 z4c_status z4c_step(z4c_plan *plan, const z4c_step_desc *desc, int *result, void *stream);
 

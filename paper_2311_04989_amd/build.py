@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libz4c.so")
-SOURCES = ["z4c_kernels.hip", "z4c_api.hip"]
+SOURCES = ["z4c_variants_p6_f64.hip", "z4c_variants_p6_f32.hip", "z4c_variants_p4.hip",
+           "z4c_kernels.hip", "z4c_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from forming packed-FP32 instructions
@@ -29,7 +30,7 @@ def _compile(src: str) -> str:
 
 
 def build() -> str:
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

@@ -39,7 +39,7 @@ z4c_status hip_fail(hipError_t e, const char *what)
     } while (0)
 
 struct LaunchGroup {
-    int tx, ty, tz, persistent;
+    int tx, ty, tz, persistent, waves;
     std::vector<Tile> tiles;
     Tile *tiles_d = nullptr;
     long long tile_base = 0;
@@ -56,7 +56,7 @@ struct StepKey {
     const double *matter;
     const double *frozen;
     double dt;
-    int nstages, ghost_policy;
+    int nstages, ghost_policy, flags;
     z4c_rk_coeffs table[8];
     int version;
     bool operator==(const StepKey &o) const { return std::memcmp(this, &o, sizeof(StepKey)) == 0; }
@@ -164,6 +164,9 @@ struct z4c_plan {
     int *nbr_d = nullptr;
     bool has_nbr = false;
     bool periodic_ok = true;   // every block has nx, ny, nz >= ng
+    bool offsets32 = true;     // offset + 22 field_stride < 2^32 for every block
+    int halo = Z4C_GHOST_NONE; // halo reads of z4c_rhs / z4c_rk_stage / z4c_constraints
+    const double *halo_frozen = nullptr;
     long long *pt_start_d = nullptr;
     long long total_pts = 0;
     unsigned long long *count_d = nullptr;
@@ -231,7 +234,7 @@ z4c_status build_groups(z4c_plan *P)
     std::vector<int> tcount(P->nblocks, 0);
     for (const SizeClass &c : P->classes) {
         const std::vector<int> key = {c.launch.tile_x, c.launch.tile_y, c.launch.tile_z,
-                                      c.launch.persistent};
+                                      c.launch.persistent, c.launch.waves};
         auto it = gidx.find(key);
         int gi;
         if (it == gidx.end()) {
@@ -242,6 +245,7 @@ z4c_status build_groups(z4c_plan *P)
             g.ty = c.launch.tile_y;
             g.tz = c.launch.tile_z;
             g.persistent = c.launch.persistent;
+            g.waves = c.launch.waves;
             P->groups.push_back(g);
         } else {
             gi = it->second;
@@ -269,7 +273,7 @@ z4c_status build_groups(z4c_plan *P)
     for (size_t ci = 0; ci < P->classes.size(); ++ci) {
         const SizeClass &c = P->classes[ci];
         const std::vector<int> key = {c.launch.tile_x, c.launch.tile_y, c.launch.tile_z,
-                                      c.launch.persistent};
+                                      c.launch.persistent, c.launch.waves};
         const int gi = gidx[key];
         for (int b : c.blocks)
             tstart[b] += P->groups[gi].tile_base;
@@ -312,6 +316,9 @@ StageArgs base_args(const z4c_plan *P)
     a.lapse = P->params.lapse;
     a.shift = P->params.shift;
     a.advect_gauge = P->params.advect_gauge;
+    a.halo = P->halo;
+    a.nbr = P->nbr_d;
+    a.frozen = P->halo_frozen;
     return a;
 }
 
@@ -322,7 +329,8 @@ z4c_status run_groups(z4c_plan *P, int mode, int arith, StageArgs a, hipStream_t
         a.ntiles = (int)g.tiles.size();
         a.persistent = g.persistent;
         a.tile_base = g.tile_base;
-        const hipError_t e = launch_stage(mode, P->params.fd_order, arith, g.tx, g.ty, g.tz, a, s);
+        const hipError_t e = launch_stage(mode, P->params.fd_order, arith, g.tx, g.ty, g.tz,
+                                          g.waves, a, s);
         if (e != hipSuccess)
             return hip_fail(e, "tile kernel launch");
     }
@@ -368,9 +376,13 @@ z4c_status validate_stage(const z4c_plan *P, const double *u0_in, const double *
 
 z4c_status enqueue_stage(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
                          const double *u2, const double *matter, const z4c_rk_coeffs *c,
-                         double dt, hipStream_t s)
+                         double dt, hipStream_t s, int halo = -1, const double *frozen = nullptr)
 {
     StageArgs a = base_args(P);
+    if (halo >= 0) {
+        a.halo = halo;
+        a.frozen = frozen;
+    }
     a.u = u0_in;
     a.matter = matter;
     a.out = u0_out;
@@ -428,6 +440,28 @@ z4c_status validate_ghost(const z4c_plan *P, int policy, const double *u, const 
     return Z4C_OK;
 }
 
+z4c_status validate_halo(const z4c_plan *P, int policy, const double *frozen)
+{
+    if (policy < 0 || policy > 3)
+        return fail(Z4C_EINVAL, "unknown ghost policy");
+    if (policy == Z4C_GHOST_NONE)
+        return Z4C_OK;
+    if (!P->offsets32)
+        return fail(Z4C_ENOTSUP, "halo reads through a ghost rule need offset + 22*field_stride "
+                                 "< 2^32 for every block");
+    if (policy == Z4C_GHOST_NEIGHBOUR && !P->has_nbr)
+        return fail(Z4C_EINVAL, "neighbour policy needs z4c_plan_set_neighbours first");
+    if (policy == Z4C_GHOST_PERIODIC && !P->periodic_ok)
+        return fail(Z4C_EINVAL, "periodic refresh needs nx, ny, nz >= ng for every block");
+    if ((policy == Z4C_GHOST_FROZEN || policy == Z4C_GHOST_NEIGHBOUR) && !frozen) {
+        if (policy == Z4C_GHOST_FROZEN)
+            return fail(Z4C_EINVAL, "frozen policy needs the frozen array");
+    }
+    if (!aligned8(frozen))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    return Z4C_OK;
+}
+
 // Buffer schedule of a step: stage s reads regs[in_s]; every stage but the
 // last writes the first of {1, 2} it does not read; the last stage writes
 // regs[0] when it does not read u2 (= regs[0]), so that the step leaves the
@@ -465,6 +499,8 @@ z4c_status validate_step(const z4c_plan *P, const z4c_step_desc *d)
         if ((c.read_u1 || c.write_u1 || c.g2 != 0.0) && !d->regs[3])
             return fail(Z4C_EINVAL, "regs[3] (accumulator) is NULL but a stage uses it");
     }
+    if (d->flags & ~(Z4C_STEP_STORED_GHOSTS | Z4C_STEP_NO_FINAL_FILL))
+        return fail(Z4C_EINVAL, "unknown step flags");
     return validate_ghost(P, d->ghost_policy, d->regs[0], d->frozen);
 }
 
@@ -474,13 +510,26 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
     z4c_status st = step_schedule(d, in, out, &res);
     if (st != Z4C_OK)
         return st;
+    // Ghost data of every stage input are read through the refresh rule
+    // (no refresh pass) unless stored ghosts are asked for or unavailable.
+    const bool stored = (d->flags & Z4C_STEP_STORED_GHOSTS) || d->ghost_policy == Z4C_GHOST_NONE
+                        || !P->offsets32;
     for (int k = 0; k < d->nstages; ++k) {
         const double *y = d->regs[0];
-        st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
-                           &d->table[k], d->dt, s);
+        if (stored) {
+            st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
+                               &d->table[k], d->dt, s, Z4C_GHOST_NONE, nullptr);
+            if (st == Z4C_OK)
+                st = enqueue_ghost(P, d->ghost_policy, d->regs[out[k]], d->frozen, s);
+        } else {
+            st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
+                               &d->table[k], d->dt, s, d->ghost_policy, d->frozen);
+        }
         if (st != Z4C_OK)
             return st;
-        st = enqueue_ghost(P, d->ghost_policy, d->regs[out[k]], d->frozen, s);
+    }
+    if (!stored && !(d->flags & Z4C_STEP_NO_FINAL_FILL)) {
+        st = enqueue_ghost(P, d->ghost_policy, d->regs[res], d->frozen, s);
         if (st != Z4C_OK)
             return st;
     }
@@ -540,7 +589,7 @@ z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, in
             c.nx = blocks[b].nx;
             c.ny = blocks[b].ny;
             c.nz = blocks[b].nz;
-            c.launch = z4c_launch{8, 8, 8, 0};
+            c.launch = z4c_launch{8, 8, 8, 0, 2};
             c.blocks.push_back(b);
             cls[key] = (int)P->classes.size();
             P->classes.push_back(c);
@@ -557,6 +606,8 @@ z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, in
         gs[b + 1] = gs[b] + ex * ey * ez - interior;
         if (B.nx < B.ng || B.ny < B.ng || B.nz < B.ng)
             P->periodic_ok = false;
+        if (B.offset + 22LL * B.field_stride > 0xFFFFFFFFLL)
+            P->offsets32 = false;
         ps[b + 1] = ps[b] + interior;
     }
     P->total_ghost = gs[nblocks];
@@ -640,10 +691,25 @@ z4c_status z4c_plan_set_params(z4c_plan *P, const z4c_params *params)
         if (st != Z4C_OK)
             return st;
     }
+    const bool order_changed = P->params.fd_order != params->fd_order;
     P->params = *params;
     if (P->device)
         P->clear_graphs();
     ++P->version;
+    if (order_changed) {
+        bool reset = false;
+        for (auto &c : P->classes)
+            if (!stage_shape_supported(params->fd_order, c.launch.tile_x, c.launch.tile_y,
+                                       c.launch.tile_z, c.launch.waves)) {
+                c.launch = z4c_launch{8, 8, 8, 0, 2};
+                reset = true;
+            }
+        if (reset) {
+            st = build_groups(P);
+            if (st != Z4C_OK)
+                return st;
+        }
+    }
     return upload_factors(P);
 }
 
@@ -658,8 +724,10 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
                 return fail(Z4C_EINVAL, "neighbour index out of range");
             if (n >= 0) {
                 const z4c_block &A = P->blocks[b], &B = P->blocks[n];
-                if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.ng != B.ng)
-                    return fail(Z4C_EINVAL, "neighbours must have equal nx, ny, nz, ng");
+                if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.ng != B.ng
+                    || A.field_stride != B.field_stride)
+                    return fail(Z4C_EINVAL,
+                                "neighbours must have equal nx, ny, nz, ng and field_stride");
                 const int ox = d % 3 - 1, oy = (d / 3) % 3 - 1, oz = d / 9 - 1;
                 if ((ox && A.nx < A.ng) || (oy && A.ny < A.ng) || (oz && A.nz < A.ng))
                     return fail(Z4C_EINVAL, "a neighbour copy needs n >= ng along its direction");
@@ -677,18 +745,36 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
     return Z4C_OK;
 }
 
+z4c_status z4c_plan_set_halo(z4c_plan *P, int policy, const double *frozen)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    z4c_status st = validate_halo(P, policy, frozen);
+    if (st != Z4C_OK)
+        return st;
+    P->halo = policy;
+    P->halo_frozen = frozen;
+    if (P->device)
+        P->clear_graphs();
+    ++P->version;
+    return Z4C_OK;
+}
+
 z4c_status z4c_plan_set_launch(z4c_plan *P, int nx, int ny, int nz, const z4c_launch *L)
 {
     if (!P || !L)
         return fail(Z4C_EINVAL, "plan and launch must not be NULL");
-    if (!stage_shape_supported(L->tile_x, L->tile_y, L->tile_z))
-        return fail(Z4C_ENOTSUP, "unsupported tile shape");
+    z4c_launch LL = *L;
+    if (LL.waves == 0)
+        LL.waves = 2;
+    if (!stage_shape_supported(P->params.fd_order, LL.tile_x, LL.tile_y, LL.tile_z, LL.waves))
+        return fail(Z4C_ENOTSUP, "unsupported tile shape / occupancy for this order");
     if (L->persistent < 0)
         return fail(Z4C_EINVAL, "persistent must be >= 0");
     bool any = false;
     for (auto &c : P->classes)
         if ((nx == 0 && ny == 0 && nz == 0) || (c.nx == nx && c.ny == ny && c.nz == nz)) {
-            c.launch = *L;
+            c.launch = LL;
             any = true;
         }
     if (!any)
@@ -840,6 +926,7 @@ z4c_status z4c_step_graph(z4c_plan *P, const z4c_step_desc *d, int *result, void
     key.dt = d->dt;
     key.nstages = d->nstages;
     key.ghost_policy = d->ghost_policy;
+    key.flags = d->flags;
     for (int s = 0; s < d->nstages; ++s)
         key.table[s] = d->table[s];
     key.version = P->version;
@@ -902,7 +989,8 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
         return st;
     hipStream_t s = (hipStream_t)stream;
     const z4c_rk_coeffs c{0.0, 1.0 / 3.0, 0.0, 0.0, 1.0, 0.5, 1, 1};
-    static const int shapes[][3] = {{8, 8, 8}, {8, 8, 4}};
+    static const int shapes[][4] = {{8, 8, 8, 2}, {8, 8, 8, 3}, {8, 8, 8, 4}, {8, 8, 4, 2},
+                                    {8, 8, 4, 4}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
@@ -911,8 +999,10 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
     for (size_t ci = 0; ci < saved.size(); ++ci) {
         float best_ms = 1e30f;
         for (const auto &sh : shapes) {
+            if (!stage_shape_supported(P->params.fd_order, sh[0], sh[1], sh[2], sh[3]))
+                continue;
             for (int pers : {0, 1}) {
-                z4c_launch L{sh[0], sh[1], sh[2], pers ? 2 * P->num_cus : 0};
+                z4c_launch L{sh[0], sh[1], sh[2], pers ? 2 * P->num_cus : 0, sh[3]};
                 // a plan view holding only this size class
                 P->classes.assign(1, saved[ci]);
                 P->classes[0].launch = L;

@@ -46,6 +46,13 @@ struct StageArgs {
     // scheme
     double ko_sigma, kappa1, kappa2, eta, chi_floor, alpha_floor;
     int lapse, shift, advect_gauge;
+    // Halo reads: how ghost points of the input are obtained.  GHOST_NONE:
+    // the stored ghost values; PERIODIC / NEIGHBOUR / FROZEN: read straight
+    // from the source a ghost refresh would copy (own interior wrapped, the
+    // neighbour's interior, or `frozen`), so no refresh pass is needed.
+    int halo;
+    const int *nbr;          // nblocks*27 (NEIGHBOUR)
+    const double *frozen;    // state layout (FROZEN, and NEIGHBOUR outer faces)
 };
 
 struct GhostArgs {
@@ -64,10 +71,18 @@ struct GhostArgs {
 // (60, 180) for order 6, r = order/2 + 1.
 void block_factors(const z4c_block &b, int fd_order, double sigma, double out[12]);
 
-// Launch entry points implemented in z4c_kernels.hip.
-hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz,
+// Launch entry points implemented in z4c_kernels.hip (tile kernels: one
+// variant per order, arithmetic, tile shape and occupancy target `waves`
+// = waves per SIMD the kernel is compiled for).
+hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz, int waves,
                         const StageArgs &a, hipStream_t s);
-bool stage_shape_supported(int tx, int ty, int tz);
+bool stage_shape_supported(int fd_order, int tx, int ty, int tz, int waves);
+hipError_t launch_p6_f64(int mode, int tx, int ty, int tz, int w, const StageArgs &a,
+                         hipStream_t s);
+hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArgs &a,
+                         hipStream_t s);
+hipError_t launch_p4(int mode, int arith, int tx, int ty, int tz, int w, const StageArgs &a,
+                     hipStream_t s);
 hipError_t launch_ghost(const GhostArgs &g, long long total_ghost, hipStream_t s);
 hipError_t launch_norm_reduce(const z4c_block *blocks, int nblocks, const long long *tile_start,
                               const int *tile_count, const double *partial, double *norms,

@@ -1,0 +1,22 @@
+// z4c_variants_p6_f32.hip -- instantiations of the tile kernels (see z4c_tile.h).
+#include "z4c_tile.h"
+
+namespace z4c {
+
+hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArgs &a,
+                         hipStream_t s)
+{
+    if (tx == 8 && ty == 8 && tz == 8 && w == 2)
+        return launch_variant<6, 8, 8, 8, 2, float>(mode, a, s);
+    if (tx == 8 && ty == 8 && tz == 8 && w == 3)
+        return launch_variant<6, 8, 8, 8, 3, float>(mode, a, s);
+    if (tx == 8 && ty == 8 && tz == 8 && w == 4)
+        return launch_variant<6, 8, 8, 8, 4, float>(mode, a, s);
+    if (tx == 8 && ty == 8 && tz == 4 && w == 2)
+        return launch_variant<6, 8, 8, 4, 2, float>(mode, a, s);
+    if (tx == 8 && ty == 8 && tz == 4 && w == 4)
+        return launch_variant<6, 8, 8, 4, 4, float>(mode, a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace z4c

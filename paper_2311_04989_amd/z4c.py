@@ -21,6 +21,7 @@ SHIFT_GAMMADRIVER, SHIFT_FROZEN = 0, 1
 ARITH_FP64, ARITH_FP32 = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
+STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL = 1, 2
 
 
 class Params(ctypes.Structure):
@@ -47,14 +48,14 @@ class RKCoeffs(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("tile_z", ctypes.c_int),
-                ("persistent", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("waves", ctypes.c_int)]
 
 
 class StepDesc(ctypes.Structure):
     _fields_ = [("regs", ctypes.c_void_p * 4), ("matter", ctypes.c_void_p),
                 ("table", ctypes.POINTER(RKCoeffs)), ("nstages", ctypes.c_int),
                 ("dt", ctypes.c_double), ("ghost_policy", ctypes.c_int),
-                ("frozen", ctypes.c_void_p)]
+                ("frozen", ctypes.c_void_p), ("flags", ctypes.c_int)]
 
 
 # Classic RK4 in the library's three-register stage form.
@@ -90,6 +91,7 @@ def lib():
         L.z4c_plan_destroy.argtypes = [vp]
         L.z4c_plan_set_params.argtypes = [vp, ctypes.POINTER(Params)]
         L.z4c_plan_set_neighbours.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.z4c_plan_set_halo.argtypes = [vp, ctypes.c_int, vp]
         L.z4c_plan_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(Launch)]
         L.z4c_plan_get_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -109,7 +111,7 @@ def lib():
         L.z4c_last_error.restype = ctypes.c_char_p
         L.z4c_plan_tiles.argtypes = [vp]
         L.z4c_plan_tiles.restype = ctypes.c_longlong
-        for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params",
+        for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params", "z4c_plan_set_halo",
                      "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
                      "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill",
                      "z4c_step", "z4c_step_graph", "z4c_plan_autotune", "z4c_check_finite"):
@@ -197,14 +199,17 @@ class Plan:
         _check(lib().z4c_plan_set_neighbours(self._h, t.ctypes.data_as(
             ctypes.POINTER(ctypes.c_int))))
 
-    def set_launch(self, nx, ny, nz, tile=(8, 8, 8), persistent=0):
-        L = Launch(tile[0], tile[1], tile[2], persistent)
+    def set_halo(self, policy, frozen=None):
+        _check(lib().z4c_plan_set_halo(self._h, int(policy), _ptr(frozen)))
+
+    def set_launch(self, nx, ny, nz, tile=(8, 8, 8), persistent=0, waves=2):
+        L = Launch(tile[0], tile[1], tile[2], persistent, waves)
         _check(lib().z4c_plan_set_launch(self._h, nx, ny, nz, ctypes.byref(L)))
 
     def get_launch(self, nx, ny, nz):
         L = Launch()
         _check(lib().z4c_plan_get_launch(self._h, nx, ny, nz, ctypes.byref(L)))
-        return (L.tile_x, L.tile_y, L.tile_z), L.persistent
+        return (L.tile_x, L.tile_y, L.tile_z), L.persistent, L.waves
 
     def rhs(self, u, matter, out, stream=None):
         _check(lib().z4c_rhs(self._h, _ptr(u), _ptr(matter), _ptr(out), _stream(stream)))
@@ -222,7 +227,7 @@ class Plan:
         _check(lib().z4c_ghost_fill(self._h, int(policy), _ptr(u), _ptr(frozen),
                                     _stream(stream)))
 
-    def _desc(self, regs, matter, table, dt, ghost, frozen):
+    def _desc(self, regs, matter, table, dt, ghost, frozen, flags=0):
         tab = (RKCoeffs * len(table))(*[_coeffs(c) for c in table])
         d = StepDesc()
         for r in range(4):
@@ -233,12 +238,14 @@ class Plan:
         d.dt = float(dt)
         d.ghost_policy = int(ghost)
         d.frozen = _ptr(frozen)
+        d.flags = int(flags)
         return d, tab
 
-    def step(self, regs, matter, table, dt, ghost, frozen=None, stream=None, graph=False) -> int:
+    def step(self, regs, matter, table, dt, ghost, frozen=None, stream=None, graph=False,
+             flags=0) -> int:
         """One Runge-Kutta step; returns the index of the register holding the
         new state."""
-        d, tab = self._desc(regs, matter, table, dt, ghost, frozen)
+        d, tab = self._desc(regs, matter, table, dt, ghost, frozen, flags)
         res = ctypes.c_int(-1)
         fn = lib().z4c_step_graph if graph else lib().z4c_step
         _check(fn(self._h, ctypes.byref(d), ctypes.byref(res), _stream(stream)))

@@ -43,6 +43,7 @@ def test_structure_layouts_match_header_sizes():
     assert ctypes.sizeof(Z.Block) == 72
     assert W.BLOCK_DTYPE.itemsize == 72
     assert ctypes.sizeof(Z.RKCoeffs) == 56
+    assert ctypes.sizeof(Z.Launch) == 20
 
 
 def test_plan_validation_errors():
@@ -84,7 +85,8 @@ def test_plan_validation_errors():
 
 
 def test_call_validation_before_device():
-    bt = W.random_batch(2, nblocks=1, nmax=8, fd_order=4)
+    bt = W.Batch([W.Block(8, 6, 7, 3, 0.1, 0.1, 0.1)])
+    bt.params = W.Params(fd_order=4)
     p = _plan(bt)
     c = Z.RK4[1]
     A, B, C, D = 0x10000, 0x20000, 0x30000, 0x40000     # never dereferenced
@@ -137,6 +139,17 @@ def test_call_validation_before_device():
     assert e.value.status == Z.EINVAL
     q.close()
     with pytest.raises(Z.Z4cError) as e:
+        p.set_halo(Z.GHOST_FROZEN, None)                # frozen rule needs the array
+    assert e.value.status == Z.EINVAL
+    with pytest.raises(Z.Z4cError) as e:
+        p.set_halo(Z.GHOST_NEIGHBOUR, None)             # no table yet
+    assert e.value.status == Z.EINVAL
+    p.set_halo(Z.GHOST_PERIODIC, None)
+    p.set_halo(Z.GHOST_NONE, None)
+    with pytest.raises(Z.Z4cError) as e:
+        p.step([A, B, C, D], None, Z.RK4, 0.1, Z.GHOST_NONE, flags=8)   # unknown flag
+    assert e.value.status == Z.EINVAL
+    with pytest.raises(Z.Z4cError) as e:
         p.step([A, B, B, D], None, Z.RK4, 0.1, Z.GHOST_NONE)   # duplicate registers
     assert e.value.status == Z.EINVAL
     with pytest.raises(Z.Z4cError) as e:
@@ -172,7 +185,7 @@ def test_tile_counts_and_launch_shapes():
     # 410 x 1 + 307 x 8 + 205 x 27 + 102 x 64 tiles of 8^3
     assert p.tiles == 410 + 307 * 8 + 205 * 27 + 102 * 64
     p.set_launch(32, 32, 32, (8, 8, 4), 0)
-    assert p.get_launch(32, 32, 32) == ((8, 8, 4), 0)
+    assert p.get_launch(32, 32, 32) == ((8, 8, 4), 0, 2)
     assert p.tiles == 410 + 307 * 8 + 205 * 27 + 102 * 128
     with pytest.raises(Z.Z4cError) as e:
         p.set_launch(0, 0, 0, (5, 5, 5), 0)

@@ -189,10 +189,19 @@ def test_launch_shape_and_persistence_do_not_change_results():
     bt = W.random_batch(11, nblocks=4, nmax=30, fd_order=6)
     note("launch-shape invariance")
     ref = gpu_rhs(bt)
-    for tile, pers in (((8, 8, 4), 0), ((8, 8, 8), 7), ((8, 8, 4), 3)):
-        plan = Z.plan_for(bt)
-        plan.set_launch(0, 0, 0, tile, pers)
-        assert np.array_equal(gpu_rhs(bt, plan=plan), ref), (tile, pers)
+    ref32 = gpu_rhs(bt, Z.ARITH_FP32)
+    stage_ref, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u)
+    stage_ref32, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, arith=Z.ARITH_FP32)
+    for tile, pers, waves in (((8, 8, 4), 0, 2), ((8, 8, 8), 7, 2), ((8, 8, 4), 3, 2),
+                              ((8, 8, 8), 0, 3), ((8, 8, 8), 0, 4), ((8, 8, 4), 5, 4)):
+        for arith in (Z.ARITH_FP64, Z.ARITH_FP32):
+            base = ref if arith == Z.ARITH_FP64 else ref32
+            plan = Z.plan_for(bt, arith)
+            plan.set_launch(0, 0, 0, tile, pers, waves)
+            assert np.array_equal(gpu_rhs(bt, plan=plan), base), (tile, pers, waves, arith)
+            out, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, plan=plan)
+            base_stage = stage_ref if arith == Z.ARITH_FP64 else stage_ref32
+            assert np.array_equal(out, base_stage), (tile, pers, waves, arith)
 
 
 # --- level sets at full size (sampled oracle) -------------------------------------------
@@ -280,6 +289,58 @@ def test_config5_full_size_rhs_one_block():
         gsub.view(gsub.u, 0, f)[...] = bt.view(g, 5, f)
     rows = compare(sub, gsub.u, O.rhs(sub), O.rhs(sub, ext=True))
     assert_parity(rows, "config5 rhs block 5\n" + report(rows))
+
+
+# --- ghosts through the refresh rule --------------------------------------------------
+
+def test_steps_reading_ghosts_through_the_rule_equal_stored_refresh():
+    """A step whose stages read ghost points through the refresh rule equals,
+    bitwise, a step that refreshes the stored ghosts after every stage."""
+    Z = z4c()
+    cases = [W.config1(), W.config5(n=16)]
+    fb = W.random_batch(8, nblocks=2, nmax=14, ng=4, fd_order=6)
+    fb.ghost = W.GHOST_FROZEN
+    fb.frozen = fb.u.copy() * (1.0 + 1e-3)
+    cases.append(fb)
+    for bt in cases:
+        note(f"rule-read vs stored ghosts: {bt.name}")
+        O.ghost_fill(bt, bt.u)
+        plan = Z.plan_for(bt)
+        frozen = dev(bt.frozen) if bt.frozen is not None else None
+        outs = []
+        for flags in (Z.STEP_STORED_GHOSTS, 0, Z.STEP_NO_FINAL_FILL):
+            regs = [dev(bt.u), dev(bt.u), dev(bt.u), zeros(bt.total_u)]
+            r = plan.step(regs, dev(bt.matter), Z.RK4, bt.dt, bt.ghost, frozen, flags=flags)
+            outs.append(host(regs[r]))
+        assert np.array_equal(outs[0], outs[1])      # whole array: final ghosts refreshed
+        for b in range(len(bt.blocks)):
+            for f in range(W.NF):
+                assert np.array_equal(bt.interior(outs[0], b, f), bt.interior(outs[2], b, f))
+
+
+def test_halo_reads_ignore_stale_stored_ghosts():
+    Z = z4c()
+    bt = W.config5(n=12)
+    O.ghost_fill(bt, bt.u)
+    ref = gpu_rhs(bt)
+    stale = bt.u.copy()
+    rng = np.random.default_rng(9)
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            v = bt.view(stale, b, f)
+            g = bt.blocks[b].ng
+            keep = v[g:-g, g:-g, g:-g].copy()
+            v[...] = rng.normal(size=v.shape)
+            v[g:-g, g:-g, g:-g] = keep
+    plan = Z.plan_for(bt)
+    fr = dev(bt.frozen)
+    plan.set_halo(Z.GHOST_NEIGHBOUR, fr)
+    u, out = dev(stale), zeros(bt.total_u)
+    plan.rhs(u, dev(bt.matter), out)
+    got = host(out)
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            assert np.array_equal(bt.interior(got, b, f), bt.interior(ref, b, f))
 
 
 # --- ghosts, finiteness ------------------------------------------------------------------
