@@ -14,6 +14,9 @@ SOURCES = ["z4c_variants_p6_f64.hip", "z4c_variants_p6_f32.hip", "z4c_variants_p
            "z4c_kernels.hip", "z4c_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # a*b + c fused only where one source expression says so, so that
+         # every launch variant rounds identically
+         "-ffp-contract=on",
          # keep the compiler from forming packed-FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

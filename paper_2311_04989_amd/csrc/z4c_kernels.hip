@@ -149,9 +149,8 @@ bool stage_shape_supported(int fd_order, int tx, int ty, int tz, int waves)
 {
     if (tx != 8 || ty != 8 || (tz != 8 && tz != 4))
         return false;
-    if (fd_order == 4)
-        return waves == 2;
-    return waves == 2 || waves == 4 || (waves == 3 && tz == 8);
+    (void)fd_order;
+    return waves == 2;
 }
 
 hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz, int waves,

@@ -33,6 +33,7 @@ namespace z4c {
 namespace tile {
 
 constexpr double PI = 3.14159265358979323846;
+constexpr int LDS_PER_CU = 163840;   // gfx950
 
 // Symmetric 3x3 index: xx 0, xy 1, xz 2, yy 3, yz 4, zz 5.
 __host__ __device__ constexpr int S(int i, int j)
@@ -449,6 +450,98 @@ __device__ __forceinline__ void setup_stager(Stager<NLD> &st, const StageArgs &a
                 st.src[q] = idx;
                 st.valid |= 1u << q;
             }
+        }
+    }
+}
+
+// Halo-tile staging for the stage kernel: as Stager, with the per-element
+// source offsets kept in LDS (one 32-bit word per element and thread) and the
+// LDS destination recomputed from the thread index, so that only the
+// prefetched values occupy registers across the kernel.  Elements beyond the
+// stored region of the block (ragged tiles) are clamped to an in-bounds
+// point: no active point's stencil reaches them.
+template <int NLD, int NT, int LX, int LY, int LZ, int PX, int PXY>
+struct LStager {
+    static constexpr int LVOL = LX * LY * LZ;
+    double pf[NLD];
+    const double *u, *frozen;   // bases the offsets refer to (uniform)
+    long long fs;
+    const unsigned *src;        // LDS, src[q * NT + t]
+    unsigned frz;               // bit q: element q comes from `frozen`
+
+    __device__ __forceinline__ void prefetch(int f, int t)
+    {
+        const double *bu = u + (long long)f * fs;
+        const double *bf = frozen + (long long)f * fs;
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            if ((q + 1) * NT <= LVOL || t + q * NT < LVOL) {
+                const unsigned o = src[q * NT + t];
+                pf[q] = ((frz >> q) & 1u ? bf : bu)[o];
+            }
+        }
+    }
+    __device__ __forceinline__ void store(double *lds, int t)
+    {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = t + q * NT;
+            if ((q + 1) * NT <= LVOL || e < LVOL) {
+                const int lx = e % LX, r1 = e / LX, ly = r1 % LY, lz = r1 / LY;
+                lds[lz * PXY + ly * PX + lx] = pf[q];
+            }
+        }
+    }
+};
+
+template <int NLD, int NT, int RAD, int LX, int LY, int LZ, int PX, int PXY>
+__device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, PXY> &st,
+                                              unsigned *src, const StageArgs &a, const Tile &T,
+                                              const z4c_block &B, int t)
+{
+    constexpr int LVOL = LX * LY * LZ;
+    const int ng = B.ng;
+    const int sy = B.nx + 2 * ng;
+    const int sz = sy * (B.ny + 2 * ng);
+    // Offsets from the block's own base without a refresh rule (no limit on
+    // the array size); from the array base with one (the plan guarantees
+    // 32-bit offsets then).
+    const bool rule = a.halo != Z4C_GHOST_NONE;
+    const unsigned own = rule ? (unsigned)B.offset : 0u;
+    st.u = rule ? a.u : a.u + B.offset;
+    st.frozen = rule ? a.frozen : nullptr;
+    st.fs = B.field_stride;
+    st.src = src;
+    st.frz = 0u;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        const int e = t + q * NT;
+        if ((q + 1) * NT <= LVOL || e < LVOL) {
+            const int lx = e % LX, r1 = e / LX, ly = r1 % LY, lz = r1 / LY;
+            int gi = T.i0 - RAD + lx, gj = T.j0 - RAD + ly, gk = T.k0 - RAD + lz;
+            gi = gi < B.nx + ng ? gi : B.nx + ng - 1;
+            gj = gj < B.ny + ng ? gj : B.ny + ng - 1;
+            gk = gk < B.nz + ng ? gk : B.nz + ng - 1;
+            const int ox = gi < 0 ? -1 : (gi >= B.nx ? 1 : 0);
+            const int oy = gj < 0 ? -1 : (gj >= B.ny ? 1 : 0);
+            const int oz = gk < 0 ? -1 : (gk >= B.nz ? 1 : 0);
+            unsigned idx = own + (unsigned)((gk + ng) * sz + (gj + ng) * sy + (gi + ng));
+            if ((ox | oy | oz) != 0 && rule) {
+                int sb = -1;
+                if (a.halo == Z4C_GHOST_PERIODIC)
+                    sb = T.block;
+                else if (a.halo == Z4C_GHOST_NEIGHBOUR)
+                    sb = a.nbr[T.block * 27 + (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)];
+                if (sb >= 0) {
+                    // same nx, ny, nz, ng and field stride as this block
+                    const int si = gi - ox * B.nx, sj = gj - oy * B.ny, sk = gk - oz * B.nz;
+                    idx = (unsigned)a.blocks[sb].offset
+                        + (unsigned)((sk + ng) * sz + (sj + ng) * sy + (si + ng));
+                } else if (a.frozen) {
+                    st.frz |= 1u << q;
+                }   // else: the stored ghost, which a refresh leaves as it is
+            }
+            src[q * NT + t] = idx;
         }
     }
 }
@@ -892,9 +985,24 @@ stage_kernel(const StageArgs a)
     constexpr int NLD = (LVOL + NT - 1) / NT;
     constexpr bool RK = MODE == MODE_RK;
     __shared__ double lds[PXY * LZ];
+    // Per-thread LDS slots for long-lived values where the LDS that the halo
+    // tile leaves at this occupancy allows: the Christoffel symbols (from the
+    // conformal metric stage to the lapse stage) and the shift gradient (from
+    // the shift stage to the At stage).  Each slot is one R per thread,
+    // consecutive threads adjacent.
+    constexpr int WG_PER_CU = (4 * WPE * 64 + NT - 1) / NT;
+    __shared__ unsigned src_lds[NLD * NT];
+    constexpr int SLOT_BUDGET =
+        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4) / (NT * (int)sizeof(R));
+    constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
+    constexpr bool DB_SLOT = SLOT_BUDGET >= (GU_SLOT ? 27 : 9);
+    constexpr int GU0 = 0, DB0 = GU_SLOT ? 18 : 0;
+    constexpr int NSLOT = (GU_SLOT ? 18 : 0) + (DB_SLOT ? 9 : 0);
+    __shared__ R slots[NSLOT > 0 ? NSLOT * NT : 1];
 
     const int t = threadIdx.x;
     const int tx = t % TX, ty = (t / TX) % TY, tz = t / (TX * TY);
+    R *const sl = slots + t;
     // Stencil centre of this thread in the LDS tile.  The offset is passed
     // through an opaque move after every staging barrier so that the
     // compiler recomputes the stencil addresses per field instead of
@@ -921,19 +1029,19 @@ stage_kernel(const StageArgs a)
         const double *ub = a.u + B.offset;
         const long long fs = B.field_stride;
 
-        Stager<NLD> st;
-        setup_stager<NLD, NT, RAD, LX, LY, LZ, PX, PXY>(st, a, T, B, t);
+        LStager<NLD, NT, LX, LY, LZ, PX, PXY> st;
+        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY>(st, src_lds, a, T, B, t);
         auto stage = [&](auto FC) __attribute__((always_inline)) {
             constexpr int NX = next_field<MODE>(decltype(FC)::value);
             __syncthreads();
-            st.store(lds);
+            st.store(lds, t);
             if constexpr (NX >= 0)
-                st.prefetch(NX);
+                st.prefetch(NX, t);
             __syncthreads();
             loff = tofs;
             asm volatile("" : "+v"(loff));
         };
-        st.prefetch(BETAX);
+        st.prefetch(BETAX, t);
 
         const Fac<R> F = load_fac<R>(a, T.block);
         auto centre = [&](int f) __attribute__((always_inline)) {
@@ -942,25 +1050,63 @@ stage_kernel(const StageArgs a)
         double *ob = a.out + B.offset;
         double *u1b = a.u1 ? a.u1 + B.offset : nullptr;
         const double *u2b = a.u2 ? a.u2 + B.offset : nullptr;
-        // Runge-Kutta combination of field f with right-hand side kf (FP64).
-        auto combine = [&](int f, R kf_r) __attribute__((always_inline)) {
-            const long long e = f * fs;
+        // Values of field f at this point in the u1 and u2 registers, loaded
+        // at the start of the stage that completes f so that the stage's LDS
+        // work covers their latency.
+        struct Old {
+            double u1, u2;
+        };
+        auto old = [&](int f) __attribute__((always_inline)) {
+            Old o{0.0, 0.0};
+            if constexpr (RK) {
+                const long long e = f * fs;
+                if (a.read_u1)
+                    o.u1 = (u1b + e)[upt];
+                if (a.use_u2 && !a.u2_is_u0)
+                    o.u2 = (u2b + e)[upt];
+            }
+            return o;
+        };
+        // State value of the field staged in LDS at this thread's point.
+        auto staged = [&]() __attribute__((always_inline)) { return lds[loff]; };
+        // Runge-Kutta combination of field f (state u0) with right-hand side kf (FP64).
+        auto combine = [&](int f, R kf_r, double u0, const Old &o) __attribute__((always_inline)) {
             const double kf = double(kf_r);
-            const double u0 = (ub + e)[upt];
-            const double n1 = (a.read_u1 ? (u1b + e)[upt] : 0.0) + a.delta * u0 + a.eps_dt * kf;
+            const double n1 = o.u1 + a.delta * u0 + a.eps_dt * kf;
             double w = a.g1 * u0 + a.g2 * n1;
             if (a.use_u2)
-                w += a.g3 * (a.u2_is_u0 ? u0 : (u2b + e)[upt]);
+                w += a.g3 * (a.u2_is_u0 ? u0 : o.u2);
             if (a.write_u1)
-                (u1b + e)[upt] = n1;
+                (u1b + f * fs)[upt] = n1;
             return w + a.beta_dt * kf;
         };
         // Finish a field that needs no enforcement.
-        auto finish = [&](int f, R kf) __attribute__((always_inline)) {
+        auto finish = [&](int f, R kf, double u0, const Old &o) __attribute__((always_inline)) {
             if constexpr (RK)
-                (ob + f * fs)[upt] = combine(f, kf);
+                (ob + f * fs)[upt] = combine(f, kf, u0, o);
             else
                 (ob + f * fs)[upt] = double(kf);
+        };
+        // Shift gradient d_j beta^k and Christoffel symbols Gt^k_q: LDS slots
+        // or registers.
+        R db_r[3][3], Gu[3][6];
+        auto DBw = [&](int kk, int jj, R v) __attribute__((always_inline)) {
+            if constexpr (DB_SLOT)
+                sl[(DB0 + 3 * kk + jj) * NT] = v;
+            else
+                db_r[kk][jj] = v;
+        };
+        auto DB = [&](int kk, int jj) __attribute__((always_inline)) -> R {
+            if constexpr (DB_SLOT)
+                return sl[(DB0 + 3 * kk + jj) * NT];
+            else
+                return db_r[kk][jj];
+        };
+        auto GU = [&](int kk, int q) __attribute__((always_inline)) -> R {
+            if constexpr (GU_SLOT)
+                return sl[(GU0 + 6 * kk + q) * NT];
+            else
+                return Gu[kk][q];
         };
 
         R g[6];
@@ -995,31 +1141,32 @@ stage_kernel(const StageArgs a)
         };
 
         // ---- shift: d beta (kept for the Lie-derivative terms), d d beta -> Gt
-        R db[3][3];   // db[k][j] = d_j beta^k
         R rG[3] = {R(0), R(0), R(0)};
+        R divb = R(0);
         sfor<3>([&](auto K_c) __attribute__((always_inline)) {
             constexpr int kk = decltype(K_c)::value;
             stage(std::integral_constant<int, BETAX + kk>{});
             if (active) {
+                const Old o = old(BETAX + kk);
+                const R Gam = R((ub + (GAMX + kk) * fs)[upt]);
                 R d[3], dd[6], ko;
                 all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
                 sfor<3>([&](auto J_c) __attribute__((always_inline)) {
                     constexpr int jj = decltype(J_c)::value;
-                    db[kk][jj] = d[jj];
+                    DBw(kk, jj, d[jj]);
                 });
+                divb += d[kk];
                 rG[kk] += symtrace(gi, dd);
                 sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                     constexpr int ii = decltype(I_c)::value;
                     rG[ii] += R(1.0 / 3.0) * (gi[S(ii, 0)] * dd[S(0, kk)] + gi[S(ii, 1)] * dd[S(1, kk)]
                                               + gi[S(ii, 2)] * dd[S(2, kk)]);
                 });
-                const R Gam = centre(GAMX + kk);
                 const R kb = (a.advect_gauge ? adv(d) : R(0)) + ko
                            + (a.shift == Z4C_SHIFT_GAMMADRIVER ? Gam : R(0)) - R(a.eta) * beta[kk];
-                finish(BETAX + kk, kb);
+                finish(BETAX + kk, kb, staged(), o);
             }
         });
-        const R divb = db[0][0] + db[1][1] + db[2][2];
 
         // ---- conformal metric
         R dg[3][6];
@@ -1030,6 +1177,8 @@ stage_kernel(const StageArgs a)
             constexpr int ii = SI(q), jj = SJ(q);
             stage(std::integral_constant<int, GXX + q>{});
             if (active) {
+                const Old o = old(GXX + q);
+                const R Aq = R((ub + (AXX + q) * fs)[upt]);
                 R d[3], dd[6], ko;
                 all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
                 sfor<3>([&](auto K_c) __attribute__((always_inline)) {
@@ -1040,13 +1189,12 @@ stage_kernel(const StageArgs a)
                 R lie = R(0);
                 sfor<3>([&](auto K_c) __attribute__((always_inline)) {
                     constexpr int kk = decltype(K_c)::value;
-                    lie += g[S(ii, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][ii];
+                    lie += g[S(ii, kk)] * DB(kk, jj) + g[S(jj, kk)] * DB(kk, ii);
                 });
-                const R Aq = centre(AXX + q);
                 const R kg = adv(d) + ko - R(2) * alpha * Aq + lie
                            - R(2.0 / 3.0) * g[q] * divb;
                 if constexpr (RK)
-                    vg[q] = combine(GXX + q, kg);
+                    vg[q] = combine(GXX + q, kg, staged(), o);
                 else
                     (ob + (GXX + q) * fs)[upt] = double(kg);
             }
@@ -1067,7 +1215,7 @@ stage_kernel(const StageArgs a)
         }
 
         // Christoffel symbols and the first-derivative part of the Ricci tensor.
-        R Gu[3][6], Gd[3];
+        R Gd[3];
         if (active) {
             R Gl[3][6];
             sfor<3>([&](auto K_c) __attribute__((always_inline)) {
@@ -1129,9 +1277,18 @@ stage_kernel(const StageArgs a)
             // Lie-derivative terms of Gamma-tilde
             sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                 constexpr int ii = decltype(I_c)::value;
-                rG[ii] += -(Gd[0] * db[ii][0] + Gd[1] * db[ii][1] + Gd[2] * db[ii][2])
+                rG[ii] += -(Gd[0] * DB(ii, 0) + Gd[1] * DB(ii, 1) + Gd[2] * DB(ii, 2))
                         + R(2.0 / 3.0) * Gd[ii] * divb;
             });
+            if constexpr (GU_SLOT) {
+                sfor<3>([&](auto K_c) __attribute__((always_inline)) {
+                    constexpr int kk = decltype(K_c)::value;
+                    sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                        constexpr int q = decltype(Q_c)::value;
+                        sl[(GU0 + 6 * kk + q) * NT] = Gu[kk][q];
+                    });
+                });
+            }
         }
 
         // ---- Gamma-tilde: d_j Gt^k -> Ricci; damping
@@ -1158,12 +1315,17 @@ stage_kernel(const StageArgs a)
         R dchi[3];
         stage(std::integral_constant<int, CHI>{});
         if (active) {
+            const Old o = old(CHI);
+            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                constexpr int q = decltype(Q_c)::value;
+                A[q] = R((ub + (AXX + q) * fs)[upt]);
+            });
             R dd[6], ko;
             all_ko<P, R, PX, PXY>(lds, loff, F, dchi, dd, ko);
             R DD[6], dc2[6];
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
-                DD[q] = dd[q] - (Gu[0][q] * dchi[0] + Gu[1][q] * dchi[1] + Gu[2][q] * dchi[2]);
+                DD[q] = dd[q] - (GU(0, q) * dchi[0] + GU(1, q) * dchi[1] + GU(2, q) * dchi[2]);
                 dc2[q] = dchi[SI(q)] * dchi[SJ(q)];
             });
             const R trDD = symtrace(gi, DD);
@@ -1177,16 +1339,12 @@ stage_kernel(const StageArgs a)
             const R kc = adv(dchi) + ko
                        + R(2.0 / 3.0) * chi * (alpha * K - divb);
             if constexpr (RK) {
-                const double v = combine(CHI, kc);
+                const double v = combine(CHI, kc, staged(), o);
                 (ob + CHI * fs)[upt] = v > a.chi_floor ? v : a.chi_floor;
             } else {
                 (ob + CHI * fs)[upt] = double(kc);
             }
-            // At, At^i_j, At^{ij}, At.At
-            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
-                constexpr int q = decltype(Q_c)::value;
-                A[q] = R((ub + (AXX + q) * fs)[upt]);
-            });
+            // At^i_j, At^{ij}, At.At
             sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                 constexpr int ii = decltype(I_c)::value;
                 sfor<3>([&](auto J_c) __attribute__((always_inline)) {
@@ -1208,7 +1366,7 @@ stage_kernel(const StageArgs a)
                 R gA = R(0);
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                     constexpr int q = decltype(Q_c)::value;
-                    gA += R(SW(q)) * Gu[ii][q] * Aup[q];
+                    gA += R(SW(q)) * GU(ii, q) * Aup[q];
                 });
                 const R Ac = Aup[S(ii, 0)] * dchi[0] + Aup[S(ii, 1)] * dchi[1]
                            + Aup[S(ii, 2)] * dchi[2];
@@ -1222,6 +1380,7 @@ stage_kernel(const StageArgs a)
         R Kpart = R(0), Tpart = R(0);
         stage(std::integral_constant<int, ALPHA>{});
         if (active) {
+            const Old o = old(ALPHA);
             R dal[3], dd[6], ko;
             all_ko<P, R, PX, PXY>(lds, loff, F, dal, dd, ko);
             R ca = R(0);   // gt^{kl} d_k chi d_l alpha
@@ -1236,7 +1395,7 @@ stage_kernel(const StageArgs a)
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
                 constexpr int ii = SI(q), jj = SJ(q);
-                DDa[q] = dd[q] - (Gu[0][q] * dal[0] + Gu[1][q] * dal[1] + Gu[2][q] * dal[2])
+                DDa[q] = dd[q] - (GU(0, q) * dal[0] + GU(1, q) * dal[1] + GU(2, q) * dal[2])
                        + (dchi[ii] * dal[jj] + dchi[jj] * dal[ii] - g[q] * ca) * ichi2;
             });
             const R D2a = chi * symtrace(gi, DDa);
@@ -1248,7 +1407,7 @@ stage_kernel(const StageArgs a)
             const R ka = (a.advect_gauge ? adv(dal) : R(0)) + ko
                        - muL * Khat;
             if constexpr (RK) {
-                const double v = combine(ALPHA, ka);
+                const double v = combine(ALPHA, ka, staged(), o);
                 (ob + ALPHA * fs)[upt] = v > a.alpha_floor ? v : a.alpha_floor;
             } else {
                 (ob + ALPHA * fs)[upt] = double(ka);
@@ -1298,7 +1457,7 @@ stage_kernel(const StageArgs a)
                 R la = R(0);
                 sfor<3>([&](auto K_c) __attribute__((always_inline)) {
                     constexpr int kk = decltype(K_c)::value;
-                    la += A[S(ii, kk)] * db[kk][jj] + A[S(jj, kk)] * db[kk][ii];
+                    la += A[S(ii, kk)] * DB(kk, jj) + A[S(jj, kk)] * DB(kk, ii);
                 });
                 PA[q] = chi * (X[q] - g[q] * trX * R(1.0 / 3.0)) + alpha * (K * A[q] - R(2) * AAm)
                       + la - R(2.0 / 3.0) * A[q] * divb;
@@ -1306,10 +1465,20 @@ stage_kernel(const StageArgs a)
         }
 
         // ---- Khat, Theta (their Gamma-tilde source terms); both complete
+        double gam0[3] = {0.0, 0.0, 0.0};   // state of Gamma-tilde, completed after Theta
+        Old gamo[3];
         sfor<2>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
             stage(std::integral_constant<int, q == 0 ? KHAT : THETA>{});
             if (active) {
+                const Old o = old(q == 0 ? KHAT : THETA);
+                if constexpr (q == 1 && RK) {
+                    sfor<3>([&](auto I_c) __attribute__((always_inline)) {
+                        constexpr int ii = decltype(I_c)::value;
+                        gam0[ii] = (ub + (GAMX + ii) * fs)[upt];
+                        gamo[ii] = old(GAMX + ii);
+                    });
+                }
                 R d[3], ko;
                 first_ko<P, R, PX, PXY>(lds, loff, F, d, ko);
                 const R c = q == 0 ? R(-4.0 / 3.0) * alpha : R(-2.0 / 3.0) * alpha;
@@ -1318,49 +1487,59 @@ stage_kernel(const StageArgs a)
                     rG[ii] += c * (gi[S(ii, 0)] * d[0] + gi[S(ii, 1)] * d[1] + gi[S(ii, 2)] * d[2]);
                 });
                 const R kq = adv(d) + ko + (q == 0 ? Kpart : Tpart);
-                finish(q == 0 ? KHAT : THETA, kq);
+                finish(q == 0 ? KHAT : THETA, kq, staged(), o);
             }
         });
         // Gamma-tilde is complete
         if (active) {
             sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                 constexpr int ii = decltype(I_c)::value;
-                finish(GAMX + ii, rG[ii]);
+                finish(GAMX + ii, rG[ii], gam0[ii], gamo[ii]);
             });
         }
 
         // ---- At_ij; then tr(At) = 0 with the new conformal metric
-        double vA[6];
+        double vA[6], vn[6];
         sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
             stage(std::integral_constant<int, AXX + q>{});
             if (active) {
+                const Old o = old(AXX + q);
+                if constexpr (q == 5 && RK) {
+                    // the new conformal metric, as stored by this thread
+                    unsigned upr = upt;
+                    asm volatile("" : "+v"(upr));
+                    sfor<6>([&](auto P_c) __attribute__((always_inline)) {
+                        constexpr int p = decltype(P_c)::value;
+                        vn[p] = (ob + (GXX + p) * fs)[upr];
+                    });
+                }
                 R d[3], ko;
                 first_ko<P, R, PX, PXY>(lds, loff, F, d, ko);
                 const R kA = adv(d) + ko + PA[q];
                 if constexpr (RK)
-                    vA[q] = combine(AXX + q, kA);
+                    vA[q] = combine(AXX + q, kA, staged(), o);
                 else
                     (ob + (AXX + q) * fs)[upt] = double(kA);
             }
         });
         if constexpr (RK) {
             if (active) {
-                const double det = vg[0] * (vg[3] * vg[5] - vg[4] * vg[4])
-                                 - vg[1] * (vg[1] * vg[5] - vg[4] * vg[2])
-                                 + vg[2] * (vg[1] * vg[4] - vg[3] * vg[2]);
+                const double det = vn[0] * (vn[3] * vn[5] - vn[4] * vn[4])
+                                 - vn[1] * (vn[1] * vn[5] - vn[4] * vn[2])
+                                 + vn[2] * (vn[1] * vn[4] - vn[3] * vn[2]);
                 const double id = 1.0 / det;
-                const double gn[6] = {(vg[3] * vg[5] - vg[4] * vg[4]) * id,
-                                      (vg[2] * vg[4] - vg[1] * vg[5]) * id,
-                                      (vg[1] * vg[4] - vg[2] * vg[3]) * id,
-                                      (vg[0] * vg[5] - vg[2] * vg[2]) * id,
-                                      (vg[2] * vg[1] - vg[0] * vg[4]) * id,
-                                      (vg[0] * vg[3] - vg[1] * vg[1]) * id};
+                const double gn[6] = {(vn[3] * vn[5] - vn[4] * vn[4]) * id,
+                                      (vn[2] * vn[4] - vn[1] * vn[5]) * id,
+                                      (vn[1] * vn[4] - vn[2] * vn[3]) * id,
+                                      (vn[0] * vn[5] - vn[2] * vn[2]) * id,
+                                      (vn[2] * vn[1] - vn[0] * vn[4]) * id,
+                                      (vn[0] * vn[3] - vn[1] * vn[1]) * id};
                 const double tr = gn[0] * vA[0] + gn[3] * vA[3] + gn[5] * vA[5]
                                 + 2.0 * (gn[1] * vA[1] + gn[2] * vA[2] + gn[4] * vA[4]);
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                     constexpr int q = decltype(Q_c)::value;
-                    (ob + (AXX + q) * fs)[upt] = vA[q] - vg[q] * tr * (1.0 / 3.0);
+                    (ob + (AXX + q) * fs)[upt] = vA[q] - vn[q] * tr * (1.0 / 3.0);
                 });
             }
         }

@@ -8,14 +8,8 @@ hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArg
 {
     if (tx == 8 && ty == 8 && tz == 8 && w == 2)
         return launch_variant<6, 8, 8, 8, 2, float>(mode, a, s);
-    if (tx == 8 && ty == 8 && tz == 8 && w == 3)
-        return launch_variant<6, 8, 8, 8, 3, float>(mode, a, s);
-    if (tx == 8 && ty == 8 && tz == 8 && w == 4)
-        return launch_variant<6, 8, 8, 8, 4, float>(mode, a, s);
     if (tx == 8 && ty == 8 && tz == 4 && w == 2)
         return launch_variant<6, 8, 8, 4, 2, float>(mode, a, s);
-    if (tx == 8 && ty == 8 && tz == 4 && w == 4)
-        return launch_variant<6, 8, 8, 4, 4, float>(mode, a, s);
     return hipErrorInvalidValue;
 }
 

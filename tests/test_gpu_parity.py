@@ -193,7 +193,7 @@ def test_launch_shape_and_persistence_do_not_change_results():
     stage_ref, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u)
     stage_ref32, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, arith=Z.ARITH_FP32)
     for tile, pers, waves in (((8, 8, 4), 0, 2), ((8, 8, 8), 7, 2), ((8, 8, 4), 3, 2),
-                              ((8, 8, 8), 0, 3), ((8, 8, 8), 0, 4), ((8, 8, 4), 5, 4)):
+                              ((8, 8, 8), 1, 2), ((8, 8, 4), 1000, 2)):
         for arith in (Z.ARITH_FP64, Z.ARITH_FP32):
             base = ref if arith == Z.ARITH_FP64 else ref32
             plan = Z.plan_for(bt, arith)
