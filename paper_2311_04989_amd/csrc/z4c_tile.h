@@ -92,8 +92,8 @@ __device__ __forceinline__ constexpr double w1(int m)
 
 // d_a d_b: first-derivative stencil along a applied to first differences
 // along b; each second difference is formed in double.
-template <int P, typename R, int SA, int SB>
-__device__ __forceinline__ R dmixraw(const double *c)
+template <int P, typename R, int SA, int SB, typename C>
+__device__ __forceinline__ R dmixraw(const C &c)
 {
     constexpr int Q = P / 2;
     R acc = R(0);
@@ -136,8 +136,8 @@ struct Fac {
 
 // All three operators along one axis from one set of samples: first and
 // second derivative and the dissipation term.
-template <int P, typename R, int ST>
-__device__ __forceinline__ void axis3(const double *c, R f1, R f2, R fk, R &d1, R &d2, R &ko)
+template <int P, typename R, int ST, typename C>
+__device__ __forceinline__ void axis3(const C &c, R f1, R f2, R fk, R &d1, R &d2, R &ko)
 {
     const double c0 = c[0];
     double p[5], m[5];
@@ -160,6 +160,20 @@ __device__ __forceinline__ void axis3(const double *c, R f1, R f2, R fk, R &d1, 
         ko = (-R(56) * R(s1) + R(28) * R(s2) - R(8) * R(s3) + R(s4)) * fk;
     }
 }
+
+// Stencil taps addressed from the lower corner of the halo box (CO elements
+// before the centre), so that every tap is a non-negative constant offset
+// from one base address.
+__device__ __forceinline__ int corner(int o)
+{
+    asm volatile("" : "+v"(o));   // keeps the rebased offset from being folded back
+    return o;
+}
+template <int CO>
+struct Corner {
+    const double *b;
+    __device__ __forceinline__ double operator[](int x) const { return b[CO + x]; }
+};
 
 // Ordering of LDS reads.  The backend issues every LDS read of a field at
 // once unless the address of a group of reads depends on the results of the
@@ -184,7 +198,8 @@ __device__ __forceinline__ int after(int off, A x, B y, C z, D w)
 template <int P, typename R, int PX, int PXY>
 __device__ __forceinline__ void first_ko(const double *L, int &off, const Fac<R> &F, R d[3], R &ko)
 {
-    const double *c = L + off;
+    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
+    const Corner<CO> c{L + corner(off - CO)};
     R d2x, d2y, d2z, kx, ky, kz;
     axis3<P, R, 1>(c, F.d1[0], F.d2[0], F.ko[0], d[0], d2x, kx);
     axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], d2y, ky);
@@ -198,20 +213,21 @@ template <int P, typename R, int PX, int PXY>
 __device__ __forceinline__ void all_ko(const double *L, int &off, const Fac<R> &F, R d[3], R dd[6],
                                        R &ko)
 {
-    const double *c = L + off;
+    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
+    Corner<CO> c{L + corner(off - CO)};
     R kx, ky, kz;
     axis3<P, R, 1>(c, F.d1[0], F.d2[0], F.ko[0], d[0], dd[0], kx);
     axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], dd[3], ky);
     axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], dd[5], kz);
     ko = kx + ky + kz;
     off = after(off, d[0], d[1], d[2], ko);
-    c = L + off;
+    c.b = L + corner(off - CO);
     dd[1] = dmixraw<P, R, 1, PX>(c) * F.mix[0];
     off = after(off, dd[1]);
-    c = L + off;
+    c.b = L + corner(off - CO);
     dd[2] = dmixraw<P, R, 1, PXY>(c) * F.mix[1];
     off = after(off, dd[2]);
-    c = L + off;
+    c.b = L + corner(off - CO);
     dd[4] = dmixraw<P, R, PX, PXY>(c) * F.mix[2];
     off = after(off, dd[4]);
 }
@@ -454,30 +470,52 @@ __device__ __forceinline__ void setup_stager(Stager<NLD> &st, const StageArgs &a
     }
 }
 
+// Element at byte offset `boff` from a (wave-uniform) base: a 32-bit offset
+// added to a scalar base, the addressing form that needs no 64-bit per-lane
+// address.
+__device__ __forceinline__ const double &at(const double *b, unsigned boff)
+{
+    return *(const double *)((const char *)b + boff);
+}
+__device__ __forceinline__ double &at(double *b, unsigned boff)
+{
+    return *(double *)((char *)b + boff);
+}
+
 // Halo-tile staging for the stage kernel: as Stager, with the per-element
-// source offsets kept in LDS (one 32-bit word per element and thread) and the
-// LDS destination recomputed from the thread index, so that only the
-// prefetched values occupy registers across the kernel.  Elements beyond the
-// stored region of the block (ragged tiles) are clamped to an in-bounds
-// point: no active point's stencil reaches them.
-template <int NLD, int NT, int LX, int LY, int LZ, int PX, int PXY>
+// sources kept in LDS (one 32-bit word per element and thread) and the LDS
+// destination recomputed from the thread index, so that only the prefetched
+// values occupy registers across the kernel.  A source word is the byte
+// offset of the element from the block's own base (its own points and
+// stored ghosts, a periodic image, or the same point of the frozen array);
+// for a point of another block (neighbour rule) it is the element offset
+// from the array base.  Elements beyond the stored region of the block
+// (ragged tiles) are clamped to an in-bounds point: no active point's
+// stencil reaches them.
+template <int NLD, int NT, int LX, int LY, int LZ, int PX, int PXY, bool GEN>
 struct LStager {
     static constexpr int LVOL = LX * LY * LZ;
     double pf[NLD];
-    const double *u, *frozen;   // bases the offsets refer to (uniform)
+    const double *own, *own_frozen, *all;   // u + offset, frozen + offset, u (uniform)
     long long fs;
-    const unsigned *src;        // LDS, src[q * NT + t]
-    unsigned frz;               // bit q: element q comes from `frozen`
+    const unsigned *src;                    // LDS, src[q * NT + t]
+    unsigned frz, far;                      // bit q: from `frozen` / from another block
 
     __device__ __forceinline__ void prefetch(int f, int t)
     {
-        const double *bu = u + (long long)f * fs;
-        const double *bf = frozen + (long long)f * fs;
+        const double *bo = own + (long long)f * fs;
+        const unsigned sp = frz | far;
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             if ((q + 1) * NT <= LVOL || t + q * NT < LVOL) {
                 const unsigned o = src[q * NT + t];
-                pf[q] = ((frz >> q) & 1u ? bf : bu)[o];
+                if (GEN && ((sp >> q) & 1u)) {
+                    pf[q] = (far >> q) & 1u ? (all + (long long)f * fs)[o]
+                                            : at(own_frozen + (long long)f * fs, o);
+                    asm volatile("");   // keeps the two loads apart (uniform base below)
+                } else {
+                    pf[q] = at(bo, o);
+                }
             }
         }
     }
@@ -494,8 +532,10 @@ struct LStager {
     }
 };
 
-template <int NLD, int NT, int RAD, int LX, int LY, int LZ, int PX, int PXY>
-__device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, PXY> &st,
+// GEN: sources may be frozen or other blocks' points (frozen and neighbour
+// rules); otherwise every source is a point of the block itself.
+template <int NLD, int NT, int RAD, int LX, int LY, int LZ, int PX, int PXY, bool GEN>
+__device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> &st,
                                               unsigned *src, const StageArgs &a, const Tile &T,
                                               const z4c_block &B, int t)
 {
@@ -503,16 +543,14 @@ __device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, P
     const int ng = B.ng;
     const int sy = B.nx + 2 * ng;
     const int sz = sy * (B.ny + 2 * ng);
-    // Offsets from the block's own base without a refresh rule (no limit on
-    // the array size); from the array base with one (the plan guarantees
-    // 32-bit offsets then).
     const bool rule = a.halo != Z4C_GHOST_NONE;
-    const unsigned own = rule ? (unsigned)B.offset : 0u;
-    st.u = rule ? a.u : a.u + B.offset;
-    st.frozen = rule ? a.frozen : nullptr;
+    st.own = a.u + B.offset;
+    st.own_frozen = a.frozen ? a.frozen + B.offset : nullptr;
+    st.all = a.u;
     st.fs = B.field_stride;
     st.src = src;
     st.frz = 0u;
+    st.far = 0u;
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
         const int e = t + q * NT;
@@ -525,23 +563,28 @@ __device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, P
             const int ox = gi < 0 ? -1 : (gi >= B.nx ? 1 : 0);
             const int oy = gj < 0 ? -1 : (gj >= B.ny ? 1 : 0);
             const int oz = gk < 0 ? -1 : (gk >= B.nz ? 1 : 0);
-            unsigned idx = own + (unsigned)((gk + ng) * sz + (gj + ng) * sy + (gi + ng));
+            unsigned w = 8u * (unsigned)((gk + ng) * sz + (gj + ng) * sy + (gi + ng));
             if ((ox | oy | oz) != 0 && rule) {
                 int sb = -1;
                 if (a.halo == Z4C_GHOST_PERIODIC)
                     sb = T.block;
-                else if (a.halo == Z4C_GHOST_NEIGHBOUR)
+                else if (GEN && a.halo == Z4C_GHOST_NEIGHBOUR)
                     sb = a.nbr[T.block * 27 + (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)];
                 if (sb >= 0) {
                     // same nx, ny, nz, ng and field stride as this block
                     const int si = gi - ox * B.nx, sj = gj - oy * B.ny, sk = gk - oz * B.nz;
-                    idx = (unsigned)a.blocks[sb].offset
-                        + (unsigned)((sk + ng) * sz + (sj + ng) * sy + (si + ng));
-                } else if (a.frozen) {
+                    const unsigned loc = (unsigned)((sk + ng) * sz + (sj + ng) * sy + (si + ng));
+                    if (sb == T.block) {
+                        w = 8u * loc;
+                    } else {
+                        w = (unsigned)a.blocks[sb].offset + loc;
+                        st.far |= 1u << q;
+                    }
+                } else if (GEN && a.frozen) {
                     st.frz |= 1u << q;
                 }   // else: the stored ghost, which a refresh leaves as it is
             }
-            src[q * NT + t] = idx;
+            src[q * NT + t] = w;
         }
     }
 }
@@ -972,7 +1015,7 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
 // field's right-hand side is finished as soon as its last contribution is
 // known and, in a stage, combined with u1/u2 and stored at once; only the new
 // conformal metric and At are held back for the det/trace enforcement.
-template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE>
+template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN>
 __global__ void __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 stage_kernel(const StageArgs a)
 {
@@ -1025,12 +1068,12 @@ stage_kernel(const StageArgs a)
         const int i = T.i0 + tx, j = T.j0 + ty, k = T.k0 + tz;
         const bool active = i < B.nx && j < B.ny && k < B.nz;
         const int pt = (k + ng) * sz + (j + ng) * sy + (i + ng);
-        const unsigned upt = (unsigned)pt;   // 32-bit offset from a uniform field base
+        const unsigned upt8 = 8u * (unsigned)pt;   // byte offset from a uniform field base
         const double *ub = a.u + B.offset;
         const long long fs = B.field_stride;
 
-        LStager<NLD, NT, LX, LY, LZ, PX, PXY> st;
-        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY>(st, src_lds, a, T, B, t);
+        LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> st;
+        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN>(st, src_lds, a, T, B, t);
         auto stage = [&](auto FC) __attribute__((always_inline)) {
             constexpr int NX = next_field<MODE>(decltype(FC)::value);
             __syncthreads();
@@ -1045,7 +1088,7 @@ stage_kernel(const StageArgs a)
 
         const Fac<R> F = load_fac<R>(a, T.block);
         auto centre = [&](int f) __attribute__((always_inline)) {
-            return active ? R((ub + f * fs)[upt]) : R(0);
+            return active ? R(at(ub + f * fs, upt8)) : R(0);
         };
         double *ob = a.out + B.offset;
         double *u1b = a.u1 ? a.u1 + B.offset : nullptr;
@@ -1061,9 +1104,9 @@ stage_kernel(const StageArgs a)
             if constexpr (RK) {
                 const long long e = f * fs;
                 if (a.read_u1)
-                    o.u1 = (u1b + e)[upt];
+                    o.u1 = at(u1b + e, upt8);
                 if (a.use_u2 && !a.u2_is_u0)
-                    o.u2 = (u2b + e)[upt];
+                    o.u2 = at(u2b + e, upt8);
             }
             return o;
         };
@@ -1077,15 +1120,15 @@ stage_kernel(const StageArgs a)
             if (a.use_u2)
                 w += a.g3 * (a.u2_is_u0 ? u0 : o.u2);
             if (a.write_u1)
-                (u1b + f * fs)[upt] = n1;
+                at(u1b + f * fs, upt8) = n1;
             return w + a.beta_dt * kf;
         };
         // Finish a field that needs no enforcement.
         auto finish = [&](int f, R kf, double u0, const Old &o) __attribute__((always_inline)) {
             if constexpr (RK)
-                (ob + f * fs)[upt] = combine(f, kf, u0, o);
+                at(ob + f * fs, upt8) = combine(f, kf, u0, o);
             else
-                (ob + f * fs)[upt] = double(kf);
+                at(ob + f * fs, upt8) = double(kf);
         };
         // Shift gradient d_j beta^k and Christoffel symbols Gt^k_q: LDS slots
         // or registers.
@@ -1112,7 +1155,7 @@ stage_kernel(const StageArgs a)
         R g[6];
         sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
-            g[q] = active ? R((ub + (GXX + q) * fs)[upt]) : ((q == 0 || q == 3 || q == 5) ? R(1) : R(0));
+            g[q] = active ? R(at(ub + (GXX + q) * fs, upt8)) : ((q == 0 || q == 3 || q == 5) ? R(1) : R(0));
         });
         R gi[6];
         {
@@ -1127,8 +1170,8 @@ stage_kernel(const StageArgs a)
             gi[5] = (g[0] * g[3] - g[1] * g[1]) * id;
         }
         const R beta[3] = {centre(BETAX), centre(BETAY), centre(BETAZ)};
-        const R chi = active ? R((ub + CHI * fs)[upt]) : R(1);
-        const R alpha = active ? R((ub + ALPHA * fs)[upt]) : R(1);
+        const R chi = active ? R(at(ub + CHI * fs, upt8)) : R(1);
+        const R alpha = active ? R(at(ub + ALPHA * fs, upt8)) : R(1);
         const R Khat = centre(KHAT), Theta = centre(THETA);
         const R K = Khat + R(2) * Theta;
         const R chis = chi > R(a.chi_floor) ? chi : R(a.chi_floor);
@@ -1148,7 +1191,7 @@ stage_kernel(const StageArgs a)
             stage(std::integral_constant<int, BETAX + kk>{});
             if (active) {
                 const Old o = old(BETAX + kk);
-                const R Gam = R((ub + (GAMX + kk) * fs)[upt]);
+                const R Gam = R(at(ub + (GAMX + kk) * fs, upt8));
                 R d[3], dd[6], ko;
                 all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
                 sfor<3>([&](auto J_c) __attribute__((always_inline)) {
@@ -1178,7 +1221,7 @@ stage_kernel(const StageArgs a)
             stage(std::integral_constant<int, GXX + q>{});
             if (active) {
                 const Old o = old(GXX + q);
-                const R Aq = R((ub + (AXX + q) * fs)[upt]);
+                const R Aq = R(at(ub + (AXX + q) * fs, upt8));
                 R d[3], dd[6], ko;
                 all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
                 sfor<3>([&](auto K_c) __attribute__((always_inline)) {
@@ -1196,7 +1239,7 @@ stage_kernel(const StageArgs a)
                 if constexpr (RK)
                     vg[q] = combine(GXX + q, kg, staged(), o);
                 else
-                    (ob + (GXX + q) * fs)[upt] = double(kg);
+                    at(ob + (GXX + q) * fs, upt8) = double(kg);
             }
         });
         if constexpr (RK) {
@@ -1209,7 +1252,7 @@ stage_kernel(const StageArgs a)
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                     constexpr int q = decltype(Q_c)::value;
                     vg[q] *= f;
-                    (ob + (GXX + q) * fs)[upt] = vg[q];
+                    at(ob + (GXX + q) * fs, upt8) = vg[q];
                 });
             }
         }
@@ -1309,42 +1352,48 @@ stage_kernel(const StageArgs a)
             }
         });
 
-        // ---- chi: R^chi_ij; chi is complete
-        R A[6], Amix[3][3], Aup[6];
-        R AA = R(0), Rs = R(0);
+        // ---- chi: R^chi_ij; chi is complete.  With the Ricci tensor and At
+        // known, everything in the sources of Khat, Theta and At except the
+        // lapse second derivatives is formed here.
+        R Aup[6];
         R dchi[3];
+        R PA[6];                      // At source without the D_i D_j alpha term
+        R Kpart = R(0), Tpart = R(0); // pointwise sources of Khat (without D^2 alpha), Theta
         stage(std::integral_constant<int, CHI>{});
         if (active) {
             const Old o = old(CHI);
+            R A[6];
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
-                A[q] = R((ub + (AXX + q) * fs)[upt]);
+                A[q] = R(at(ub + (AXX + q) * fs, upt8));
             });
             R dd[6], ko;
             all_ko<P, R, PX, PXY>(lds, loff, F, dchi, dd, ko);
-            R DD[6], dc2[6];
-            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
-                constexpr int q = decltype(Q_c)::value;
-                DD[q] = dd[q] - (GU(0, q) * dchi[0] + GU(1, q) * dchi[1] + GU(2, q) * dchi[2]);
-                dc2[q] = dchi[SI(q)] * dchi[SJ(q)];
-            });
-            const R trDD = symtrace(gi, DD);
-            const R dchi2 = symtrace(gi, dc2);
-            const R i4c2 = ichi2 * ichi2;   // 1 / (4 chi^2)
-            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
-                constexpr int q = decltype(Q_c)::value;
-                Rij[q] += (DD[q] + g[q] * trDD) * ichi2 - (dc2[q] + R(3) * g[q] * dchi2) * i4c2;
-            });
-            Rs = chi * symtrace(gi, Rij);
+            {
+                R DD[6], dc2[6];
+                sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                    constexpr int q = decltype(Q_c)::value;
+                    DD[q] = dd[q] - (GU(0, q) * dchi[0] + GU(1, q) * dchi[1] + GU(2, q) * dchi[2]);
+                    dc2[q] = dchi[SI(q)] * dchi[SJ(q)];
+                });
+                const R trDD = symtrace(gi, DD);
+                const R dchi2 = symtrace(gi, dc2);
+                const R i4c2 = ichi2 * ichi2;   // 1 / (4 chi^2)
+                sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                    constexpr int q = decltype(Q_c)::value;
+                    Rij[q] += (DD[q] + g[q] * trDD) * ichi2 - (dc2[q] + R(3) * g[q] * dchi2) * i4c2;
+                });
+            }
             const R kc = adv(dchi) + ko
                        + R(2.0 / 3.0) * chi * (alpha * K - divb);
             if constexpr (RK) {
                 const double v = combine(CHI, kc, staged(), o);
-                (ob + CHI * fs)[upt] = v > a.chi_floor ? v : a.chi_floor;
+                at(ob + CHI * fs, upt8) = v > a.chi_floor ? v : a.chi_floor;
             } else {
-                (ob + CHI * fs)[upt] = double(kc);
+                at(ob + CHI * fs, upt8) = double(kc);
             }
             // At^i_j, At^{ij}, At.At
+            R Amix[3][3];
             sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                 constexpr int ii = decltype(I_c)::value;
                 sfor<3>([&](auto J_c) __attribute__((always_inline)) {
@@ -1353,6 +1402,7 @@ stage_kernel(const StageArgs a)
                                  + gi[S(ii, 2)] * A[S(2, jj)];
                 });
             });
+            R AA = R(0);
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
                 constexpr int ii = SI(q), jj = SJ(q);
@@ -1372,12 +1422,56 @@ stage_kernel(const StageArgs a)
                            + Aup[S(ii, 2)] * dchi[2];
                 rG[ii] += R(2) * alpha * (gA - R(1.5) / chis * Ac);
             });
+            // matter
+            R rho = R(0), Si[3] = {R(0), R(0), R(0)}, Sij[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+            if (a.matter) {
+                const double *mb = a.matter + B.moffset;
+                rho = R(at(mb, upt8));
+                sfor<3>([&](auto Q_c) __attribute__((always_inline)) {
+                    constexpr int q = decltype(Q_c)::value;
+                    Si[q] = R(at(mb + (1 + q) * fs, upt8));
+                });
+                sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                    constexpr int q = decltype(Q_c)::value;
+                    Sij[q] = R(at(mb + (4 + q) * fs, upt8));
+                });
+            }
+            const R trS = chi * symtrace(gi, Sij);
+            sfor<3>([&](auto I_c) __attribute__((always_inline)) {
+                constexpr int ii = decltype(I_c)::value;
+                rG[ii] += R(-16) * pi * alpha
+                        * (gi[S(ii, 0)] * Si[0] + gi[S(ii, 1)] * Si[1] + gi[S(ii, 2)] * Si[2]);
+            });
+            const R Rs = chi * symtrace(gi, Rij);
+            Kpart = alpha * (AA + K * K * R(1.0 / 3.0)) + R(4) * pi * alpha * (trS + rho)
+                  + alpha * kap1 * (R(1) - kap2) * Theta;
+            Tpart = R(0.5) * alpha * (Rs - AA + R(2.0 / 3.0) * K * K)
+                  - alpha * (R(8) * pi * rho + kap1 * (R(2) + kap2) * Theta);
+            // At: chi [alpha (R - 8 pi S)]^tf + alpha (K At - 2 At At) + Lie
+            // (the -chi [D D alpha]^tf part follows in the lapse stage)
+            R Y[6];
+            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                constexpr int q = decltype(Q_c)::value;
+                Y[q] = alpha * (Rij[q] - R(8) * pi * Sij[q]);
+            });
+            const R trY = symtrace(gi, Y);
+            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
+                constexpr int q = decltype(Q_c)::value;
+                constexpr int ii = SI(q), jj = SJ(q);
+                const R AAm = A[S(ii, 0)] * Amix[0][jj] + A[S(ii, 1)] * Amix[1][jj]
+                            + A[S(ii, 2)] * Amix[2][jj];
+                R la = R(0);
+                sfor<3>([&](auto K_c) __attribute__((always_inline)) {
+                    constexpr int kk = decltype(K_c)::value;
+                    la += A[S(ii, kk)] * DB(kk, jj) + A[S(jj, kk)] * DB(kk, ii);
+                });
+                PA[q] = chi * (Y[q] - g[q] * trY * R(1.0 / 3.0)) + alpha * (K * A[q] - R(2) * AAm)
+                      + la - R(2.0 / 3.0) * A[q] * divb;
+            });
         }
 
-        // ---- lapse: D_i D_j alpha; alpha is complete; pointwise parts of
-        // Khat, Theta and At
-        R PA[6];
-        R Kpart = R(0), Tpart = R(0);
+        // ---- lapse: D_i D_j alpha; alpha is complete; the lapse terms of
+        // the Khat and At sources
         stage(std::integral_constant<int, ALPHA>{});
         if (active) {
             const Old o = old(ALPHA);
@@ -1398,7 +1492,7 @@ stage_kernel(const StageArgs a)
                 DDa[q] = dd[q] - (GU(0, q) * dal[0] + GU(1, q) * dal[1] + GU(2, q) * dal[2])
                        + (dchi[ii] * dal[jj] + dchi[jj] * dal[ii] - g[q] * ca) * ichi2;
             });
-            const R D2a = chi * symtrace(gi, DDa);
+            const R trDDa = symtrace(gi, DDa);
             R muL = R(0);
             if (a.lapse == Z4C_LAPSE_1PLUSLOG)
                 muL = R(2) * alpha;
@@ -1408,9 +1502,9 @@ stage_kernel(const StageArgs a)
                        - muL * Khat;
             if constexpr (RK) {
                 const double v = combine(ALPHA, ka, staged(), o);
-                (ob + ALPHA * fs)[upt] = v > a.alpha_floor ? v : a.alpha_floor;
+                at(ob + ALPHA * fs, upt8) = v > a.alpha_floor ? v : a.alpha_floor;
             } else {
-                (ob + ALPHA * fs)[upt] = double(ka);
+                at(ob + ALPHA * fs, upt8) = double(ka);
             }
             // -2 At^ij d_j alpha
             sfor<3>([&](auto I_c) __attribute__((always_inline)) {
@@ -1418,49 +1512,10 @@ stage_kernel(const StageArgs a)
                 rG[ii] += R(-2) * (Aup[S(ii, 0)] * dal[0] + Aup[S(ii, 1)] * dal[1]
                                    + Aup[S(ii, 2)] * dal[2]);
             });
-            // matter
-            R rho = R(0), Si[3] = {R(0), R(0), R(0)}, Sij[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-            if (a.matter) {
-                const double *mb = a.matter + B.moffset;
-                rho = R(mb[upt]);
-                sfor<3>([&](auto Q_c) __attribute__((always_inline)) {
-                    constexpr int q = decltype(Q_c)::value;
-                    Si[q] = R((mb + (1 + q) * fs)[upt]);
-                });
-                sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
-                    constexpr int q = decltype(Q_c)::value;
-                    Sij[q] = R((mb + (4 + q) * fs)[upt]);
-                });
-            }
-            const R trS = chi * symtrace(gi, Sij);
-            sfor<3>([&](auto I_c) __attribute__((always_inline)) {
-                constexpr int ii = decltype(I_c)::value;
-                rG[ii] += R(-16) * pi * alpha
-                        * (gi[S(ii, 0)] * Si[0] + gi[S(ii, 1)] * Si[1] + gi[S(ii, 2)] * Si[2]);
-            });
-            Kpart = -D2a + alpha * (AA + K * K * R(1.0 / 3.0)) + R(4) * pi * alpha * (trS + rho)
-                  + alpha * kap1 * (R(1) - kap2) * Theta;
-            Tpart = R(0.5) * alpha * (Rs - AA + R(2.0 / 3.0) * K * K)
-                  - alpha * (R(8) * pi * rho + kap1 * (R(2) + kap2) * Theta);
-            // At: chi [-D D alpha + alpha (R - 8 pi S)]^tf + alpha (K At - 2 At At) + Lie
-            R X[6];
+            Kpart -= chi * trDDa;
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
-                X[q] = -DDa[q] + alpha * (Rij[q] - R(8) * pi * Sij[q]);
-            });
-            const R trX = symtrace(gi, X);
-            sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
-                constexpr int q = decltype(Q_c)::value;
-                constexpr int ii = SI(q), jj = SJ(q);
-                const R AAm = A[S(ii, 0)] * Amix[0][jj] + A[S(ii, 1)] * Amix[1][jj]
-                            + A[S(ii, 2)] * Amix[2][jj];
-                R la = R(0);
-                sfor<3>([&](auto K_c) __attribute__((always_inline)) {
-                    constexpr int kk = decltype(K_c)::value;
-                    la += A[S(ii, kk)] * DB(kk, jj) + A[S(jj, kk)] * DB(kk, ii);
-                });
-                PA[q] = chi * (X[q] - g[q] * trX * R(1.0 / 3.0)) + alpha * (K * A[q] - R(2) * AAm)
-                      + la - R(2.0 / 3.0) * A[q] * divb;
+                PA[q] -= chi * (DDa[q] - g[q] * trDDa * R(1.0 / 3.0));
             });
         }
 
@@ -1475,7 +1530,7 @@ stage_kernel(const StageArgs a)
                 if constexpr (q == 1 && RK) {
                     sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                         constexpr int ii = decltype(I_c)::value;
-                        gam0[ii] = (ub + (GAMX + ii) * fs)[upt];
+                        gam0[ii] = at(ub + (GAMX + ii) * fs, upt8);
                         gamo[ii] = old(GAMX + ii);
                     });
                 }
@@ -1507,11 +1562,11 @@ stage_kernel(const StageArgs a)
                 const Old o = old(AXX + q);
                 if constexpr (q == 5 && RK) {
                     // the new conformal metric, as stored by this thread
-                    unsigned upr = upt;
+                    unsigned upr = upt8;
                     asm volatile("" : "+v"(upr));
                     sfor<6>([&](auto P_c) __attribute__((always_inline)) {
                         constexpr int p = decltype(P_c)::value;
-                        vn[p] = (ob + (GXX + p) * fs)[upr];
+                        vn[p] = at(ob + (GXX + p) * fs, upr);
                     });
                 }
                 R d[3], ko;
@@ -1520,7 +1575,7 @@ stage_kernel(const StageArgs a)
                 if constexpr (RK)
                     vA[q] = combine(AXX + q, kA, staged(), o);
                 else
-                    (ob + (AXX + q) * fs)[upt] = double(kA);
+                    at(ob + (AXX + q) * fs, upt8) = double(kA);
             }
         });
         if constexpr (RK) {
@@ -1539,7 +1594,7 @@ stage_kernel(const StageArgs a)
                                 + 2.0 * (gn[1] * vA[1] + gn[2] * vA[2] + gn[4] * vA[4]);
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                     constexpr int q = decltype(Q_c)::value;
-                    (ob + (AXX + q) * fs)[upt] = vA[q] - vn[q] * tr * (1.0 / 3.0);
+                    at(ob + (AXX + q) * fs, upt8) = vA[q] - vn[q] * tr * (1.0 / 3.0);
                 });
             }
         }
@@ -1563,10 +1618,19 @@ hipError_t launch_variant(int mode, const StageArgs &a, hipStream_t s)
     if (grid <= 0)
         return hipSuccess;
     const dim3 blk(TX * TY * TZ);
-    if (mode == MODE_RHS)
-        tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RHS><<<grid, blk, 0, s>>>(a);
-    else
-        tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK><<<grid, blk, 0, s>>>(a);
+    // halo sources beyond the block itself only under the frozen and neighbour rules
+    const bool gen = a.halo == Z4C_GHOST_FROZEN || a.halo == Z4C_GHOST_NEIGHBOUR;
+    if (mode == MODE_RHS) {
+        if (gen)
+            tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RHS, true><<<grid, blk, 0, s>>>(a);
+        else
+            tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RHS, false><<<grid, blk, 0, s>>>(a);
+    } else {
+        if (gen)
+            tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, true><<<grid, blk, 0, s>>>(a);
+        else
+            tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, false><<<grid, blk, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
