@@ -43,10 +43,11 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--cpu-sample-blocks", type=int, default=192)
     return ap.parse_args()
 
@@ -186,9 +187,74 @@ def main():
         out["fp32"] = {"value": v32, "unit": "pt-stage/s", "ms_per_step": r32["ms"],
                        "speedup_vs_fp64": v32 / value,
                        "stage_kernel_ms": r32["stage_ms"].round(4).tolist()}
+    if not args.no_batching:
+        out["batching"] = batching(stream, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
+
+
+def batching(stream, reps):
+    """One fused RK4 stage of 512 MeshBlocks of 16^3 (4 ghosts, 6th order,
+    gauge wave + noise): 512 per-block launches (one plan per block, the
+    same arrays) vs one grid launch of all tiles vs one persistent launch."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    bt = W.config3()
+    n_int = bt.ninterior
+    u = torch.from_numpy(bt.u).to("cuda:0")
+    out = torch.empty_like(u)
+    u1 = torch.zeros_like(u)
+    c = Z.RK4[0]
+    plan = Z.plan_for(bt)
+    params = Z.make_params(bt.params, Z.ARITH_FP64)
+    tab = bt.block_table()
+    singles = [Z.Plan(params, Z.make_blocks(tab[i:i + 1])) for i in range(len(bt.blocks))]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), float(np.min(ms))
+
+    def per_block():
+        for p in singles:
+            p.rk_stage(u, out, u1, u, None, c, bt.dt, stream=stream)
+
+    def whole():
+        plan.rk_stage(u, out, u1, u, None, c, bt.dt, stream=stream)
+
+    res = {"workload": "512 MeshBlocks 16^3 + 4 ghosts, 6th-order FD, gauge wave + 1e-10 noise, "
+                       "one fused RHS+RK4 stage (stored ghosts)",
+           "interior_points": n_int}
+    log("[bench] batching: 512 per-block launches")
+    res["per_block_launches_ms"] = timed(per_block)
+    plan.set_launch(16, 16, 16, (8, 8, 8), 0, 2)
+    res["grid_launch_ms"] = timed(whole)
+    nper = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    plan.set_launch(16, 16, 16, (8, 8, 8), nper, 2)
+    res["persistent_launch_ms"] = timed(whole)
+    res["persistent_workgroups"] = nper
+    res["note"] = "(median, min) over the timed repetitions, ms per stage"
+    res["pt_stage_per_s"] = {k[:-3]: n_int / (res[k][0] * 1e-3)
+                             for k in ("per_block_launches_ms", "grid_launch_ms",
+                                       "persistent_launch_ms")}
+    log(f"[bench] batching: {res}")
+    for p in singles:
+        p.close()
+    plan.close()
+    return res
 
 
 def cpu_baseline(bt, nsample):
