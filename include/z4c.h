@@ -142,7 +142,8 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *plan, const int *neighbours);
  * persistent: 0 = one workgroup per tile, otherwise that many workgroups
  * each take a contiguous run of tiles; waves: occupancy the kernel variant
  * is compiled for, in waves per SIMD (0 = 2; its register budget is
- * 512/waves per lane).  Supported: 8x8x8 and 8x8x4 with waves 2. */
+ * 512/waves per lane).  Supported: 8x8x8 and 8x8x4 with waves 2, and for
+ * order 6 also 8x8x4 with waves 1. */
 typedef struct {
     int tile_x, tile_y, tile_z;
     int persistent;

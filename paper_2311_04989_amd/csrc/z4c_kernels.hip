@@ -149,8 +149,9 @@ bool stage_shape_supported(int fd_order, int tx, int ty, int tz, int waves)
 {
     if (tx != 8 || ty != 8 || (tz != 8 && tz != 4))
         return false;
-    (void)fd_order;
-    return waves == 2;
+    // one wave per SIMD (a 256-register budget plus as many accumulation
+    // registers) for 8x8x4 tiles of the order-6 kernels
+    return waves == 2 || (waves == 1 && tz == 4 && fd_order == 6);
 }
 
 hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz, int waves,

@@ -195,7 +195,9 @@ __device__ __forceinline__ int after(int off, A x, B y, C z, D w)
 
 // First derivatives and dissipation of the field staged in L; `off` is the
 // thread's stencil centre in L and is re-ordered after the reads.
-template <int P, typename R, int PX, int PXY>
+// CHAIN: order the groups of LDS reads through `after` (register budget of
+// two or more waves per SIMD); otherwise the compiler may issue them freely.
+template <int P, typename R, int PX, int PXY, bool CHAIN = true>
 __device__ __forceinline__ void first_ko(const double *L, int &off, const Fac<R> &F, R d[3], R &ko)
 {
     constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
@@ -205,11 +207,12 @@ __device__ __forceinline__ void first_ko(const double *L, int &off, const Fac<R>
     axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], d2y, ky);
     axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], d2z, kz);
     ko = kx + ky + kz;
-    off = after(off, d[0], d[1], d[2], ko);
+    if constexpr (CHAIN)
+        off = after(off, d[0], d[1], d[2], ko);
 }
 
 // First and second derivatives and dissipation of the field staged in L.
-template <int P, typename R, int PX, int PXY>
+template <int P, typename R, int PX, int PXY, bool CHAIN = true>
 __device__ __forceinline__ void all_ko(const double *L, int &off, const Fac<R> &F, R d[3], R dd[6],
                                        R &ko)
 {
@@ -220,16 +223,88 @@ __device__ __forceinline__ void all_ko(const double *L, int &off, const Fac<R> &
     axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], dd[3], ky);
     axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], dd[5], kz);
     ko = kx + ky + kz;
-    off = after(off, d[0], d[1], d[2], ko);
-    c.b = L + corner(off - CO);
+    if constexpr (CHAIN) {
+        off = after(off, d[0], d[1], d[2], ko);
+        c.b = L + corner(off - CO);
+    }
     dd[1] = dmixraw<P, R, 1, PX>(c) * F.mix[0];
-    off = after(off, dd[1]);
+    off = after(off, dd[1], ko, d[0], d[2]);   // at most two groups in flight
     c.b = L + corner(off - CO);
     dd[2] = dmixraw<P, R, 1, PXY>(c) * F.mix[1];
-    off = after(off, dd[2]);
-    c.b = L + corner(off - CO);
+    if constexpr (CHAIN) {
+        off = after(off, dd[2]);
+        c.b = L + corner(off - CO);
+    }
     dd[4] = dmixraw<P, R, PX, PXY>(c) * F.mix[2];
-    off = after(off, dd[4]);
+    if constexpr (CHAIN)
+        off = after(off, dd[4]);
+}
+
+// Mixed second derivatives in two passes (when the LDS allows): every
+// thread first writes unscaled x- and y-first-derivative sums of the staged
+// field over the tile extended by the stencil half width in the other
+// directions (x sums: y and z extended; y sums: z extended); after a
+// barrier, d_x d_y, d_x d_z and d_y d_z are first-derivative stencils on
+// those sums (the same tensor-product stencil as dmixraw).
+template <int P, int TX, int TY, int TZ>
+struct MixDims {
+    static constexpr int Q = P / 2;
+    static constexpr int DY = TY + 2 * Q, DZ = TZ + 2 * Q;
+    static constexpr int NXS = TX * DY * DZ;   // x sums
+    static constexpr int NYS = TX * TY * DZ;   // y sums
+};
+
+template <int P, typename R, int TX, int TY, int TZ, int PX, int PXY>
+__device__ __forceinline__ void mix_prep(const double *L, R *dxb, R *dyb, int t)
+{
+    using M = MixDims<P, TX, TY, TZ>;
+    constexpr int NT = TX * TY * TZ, RAD = P / 2 + 1, Q = M::Q;
+#pragma unroll
+    for (int q = 0; q < (M::NXS + NT - 1) / NT; ++q) {
+        const int e = t + q * NT;
+        if ((q + 1) * NT <= M::NXS || e < M::NXS) {
+            const int ex = e % TX, r = e / TX, ey = r % M::DY, ez = r / M::DY;
+            dxb[e] = d1raw<P, R, 1>(L + (ez - Q + RAD) * PXY + (ey - Q + RAD) * PX + (ex + RAD));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (M::NYS + NT - 1) / NT; ++q) {
+        const int e = t + q * NT;
+        if ((q + 1) * NT <= M::NYS || e < M::NYS) {
+            const int ex = e % TX, r = e / TX, ey = r % TY, ez = r / TY;
+            dyb[e] = d1raw<P, R, PX>(L + (ez - Q + RAD) * PXY + (ey + RAD) * PX + (ex + RAD));
+        }
+    }
+}
+
+template <int P, typename R, int ST>
+__device__ __forceinline__ R d1sum(const R *c)
+{
+    if constexpr (P == 4)
+        return R(8) * (c[ST] - c[-ST]) - (c[2 * ST] - c[-2 * ST]);
+    else
+        return R(45) * (c[ST] - c[-ST]) - R(9) * (c[2 * ST] - c[-2 * ST]) + (c[3 * ST] - c[-3 * ST]);
+}
+
+// As all_ko, with the mixed derivatives from the two-pass sums.
+template <int P, typename R, int PX, int PXY, int TX, int TY, int TZ>
+__device__ __forceinline__ void all_ko_sums(const double *L, int off, const Fac<R> &F, R d[3],
+                                            R dd[6], R &ko, const R *dxb, const R *dyb, int tx,
+                                            int ty, int tz)
+{
+    using M = MixDims<P, TX, TY, TZ>;
+    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
+    const Corner<CO> c{L + corner(off - CO)};
+    R kx, ky, kz;
+    axis3<P, R, 1>(c, F.d1[0], F.d2[0], F.ko[0], d[0], dd[0], kx);
+    axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], dd[3], ky);
+    axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], dd[5], kz);
+    ko = kx + ky + kz;
+    const R *px = dxb + ((tz + M::Q) * M::DY + (ty + M::Q)) * TX + tx;
+    const R *py = dyb + ((tz + M::Q) * TY + ty) * TX + tx;
+    dd[1] = d1sum<P, R, TX>(px) * F.mix[0];
+    dd[2] = d1sum<P, R, TX * M::DY>(px) * F.mix[1];
+    dd[4] = d1sum<P, R, TX * TY>(py) * F.mix[2];
 }
 
 // Unfused helpers used by the constraint kernel.
@@ -1027,7 +1102,13 @@ stage_kernel(const StageArgs a)
     constexpr int LVOL = LX * LY * LZ;
     constexpr int NLD = (LVOL + NT - 1) / NT;
     constexpr bool RK = MODE == MODE_RK;
+    constexpr bool CHAIN = WPE > 1;
+    // one workgroup per CU: LDS for the two-pass mixed derivatives
+    constexpr bool MIX2 = WPE == 1;
+    using MD = MixDims<P, TX, TY, TZ>;
     __shared__ double lds[PXY * LZ];
+    __shared__ R dxb[MIX2 ? MD::NXS : 1];
+    __shared__ R dyb[MIX2 ? MD::NYS : 1];
     // Per-thread LDS slots for long-lived values where the LDS that the halo
     // tile leaves at this occupancy allows: the Christoffel symbols (from the
     // conformal metric stage to the lapse stage) and the shift gradient (from
@@ -1036,7 +1117,8 @@ stage_kernel(const StageArgs a)
     constexpr int WG_PER_CU = (4 * WPE * 64 + NT - 1) / NT;
     __shared__ unsigned src_lds[NLD * NT];
     constexpr int SLOT_BUDGET =
-        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4) / (NT * (int)sizeof(R));
+        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4
+         - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)) / (NT * (int)sizeof(R));
     constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
     constexpr bool DB_SLOT = SLOT_BUDGET >= (GU_SLOT ? 27 : 9);
     constexpr int GU0 = 0, DB0 = GU_SLOT ? 18 : 0;
@@ -1081,12 +1163,26 @@ stage_kernel(const StageArgs a)
             if constexpr (NX >= 0)
                 st.prefetch(NX, t);
             __syncthreads();
+            constexpr int FF = decltype(FC)::value;
+            if constexpr (MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
+                                   || (FF >= BETAX && FF <= BETAZ))) {
+                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds, dxb, dyb, t);
+                __syncthreads();
+            }
             loff = tofs;
             asm volatile("" : "+v"(loff));
         };
         st.prefetch(BETAX, t);
 
         const Fac<R> F = load_fac<R>(a, T.block);
+        // first and second derivatives and dissipation of the staged field
+        auto derivs2 = [&](R d[3], R dd[6], R &ko) __attribute__((always_inline)) {
+            if constexpr (MIX2)
+                all_ko_sums<P, R, PX, PXY, TX, TY, TZ>(lds, loff, F, d, dd, ko, dxb, dyb, tx, ty,
+                                                       tz);
+            else
+                all_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, dd, ko);
+        };
         auto centre = [&](int f) __attribute__((always_inline)) {
             return active ? R(at(ub + f * fs, upt8)) : R(0);
         };
@@ -1193,7 +1289,7 @@ stage_kernel(const StageArgs a)
                 const Old o = old(BETAX + kk);
                 const R Gam = R(at(ub + (GAMX + kk) * fs, upt8));
                 R d[3], dd[6], ko;
-                all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
+                derivs2(d, dd, ko);
                 sfor<3>([&](auto J_c) __attribute__((always_inline)) {
                     constexpr int jj = decltype(J_c)::value;
                     DBw(kk, jj, d[jj]);
@@ -1223,7 +1319,7 @@ stage_kernel(const StageArgs a)
                 const Old o = old(GXX + q);
                 const R Aq = R(at(ub + (AXX + q) * fs, upt8));
                 R d[3], dd[6], ko;
-                all_ko<P, R, PX, PXY>(lds, loff, F, d, dd, ko);
+                derivs2(d, dd, ko);
                 sfor<3>([&](auto K_c) __attribute__((always_inline)) {
                     constexpr int kk = decltype(K_c)::value;
                     dg[kk][q] = d[kk];
@@ -1340,7 +1436,7 @@ stage_kernel(const StageArgs a)
             stage(std::integral_constant<int, GAMX + kk>{});
             if (active) {
                 R d[3], ko;
-                first_ko<P, R, PX, PXY>(lds, loff, F, d, ko);
+                first_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, ko);
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                     constexpr int q = decltype(Q_c)::value;
                     constexpr int ii = SI(q), jj = SJ(q);
@@ -1368,7 +1464,7 @@ stage_kernel(const StageArgs a)
                 A[q] = R(at(ub + (AXX + q) * fs, upt8));
             });
             R dd[6], ko;
-            all_ko<P, R, PX, PXY>(lds, loff, F, dchi, dd, ko);
+            derivs2(dchi, dd, ko);
             {
                 R DD[6], dc2[6];
                 sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
@@ -1476,7 +1572,7 @@ stage_kernel(const StageArgs a)
         if (active) {
             const Old o = old(ALPHA);
             R dal[3], dd[6], ko;
-            all_ko<P, R, PX, PXY>(lds, loff, F, dal, dd, ko);
+            derivs2(dal, dd, ko);
             R ca = R(0);   // gt^{kl} d_k chi d_l alpha
             sfor<3>([&](auto P0_c) __attribute__((always_inline)) {
                 constexpr int p0 = decltype(P0_c)::value;
@@ -1535,7 +1631,7 @@ stage_kernel(const StageArgs a)
                     });
                 }
                 R d[3], ko;
-                first_ko<P, R, PX, PXY>(lds, loff, F, d, ko);
+                first_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, ko);
                 const R c = q == 0 ? R(-4.0 / 3.0) * alpha : R(-2.0 / 3.0) * alpha;
                 sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                     constexpr int ii = decltype(I_c)::value;
@@ -1570,7 +1666,7 @@ stage_kernel(const StageArgs a)
                     });
                 }
                 R d[3], ko;
-                first_ko<P, R, PX, PXY>(lds, loff, F, d, ko);
+                first_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, ko);
                 const R kA = adv(d) + ko + PA[q];
                 if constexpr (RK)
                     vA[q] = combine(AXX + q, kA, staged(), o);

@@ -184,24 +184,64 @@ def test_random_shapes_rhs_and_stage(seed):
     assert_parity(rows, f"random {seed} stage\n" + report(rows))
 
 
+def _launch_plan(bt, arith, tile, pers, waves):
+    Z = z4c()
+    plan = Z.plan_for(bt, arith)
+    plan.set_launch(0, 0, 0, tile, pers, waves)
+    return plan
+
+
 def test_launch_shape_and_persistence_do_not_change_results():
+    """Within one kernel family (the same per-point arithmetic) results are
+    bitwise independent of tile shape, persistence and tile order: two
+    waves per SIMD (8x8x8 and 8x8x4 tiles), and one wave per SIMD (8x8x4,
+    mixed derivatives in two passes, compared with the oracle in
+    test_one_wave_variant_parity)."""
     Z = z4c()
     bt = W.random_batch(11, nblocks=4, nmax=30, fd_order=6)
     note("launch-shape invariance")
-    ref = gpu_rhs(bt)
-    ref32 = gpu_rhs(bt, Z.ARITH_FP32)
-    stage_ref, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u)
-    stage_ref32, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, arith=Z.ARITH_FP32)
-    for tile, pers, waves in (((8, 8, 4), 0, 2), ((8, 8, 8), 7, 2), ((8, 8, 4), 3, 2),
-                              ((8, 8, 8), 1, 2), ((8, 8, 4), 1000, 2)):
+    families = {2: [((8, 8, 8), 0), ((8, 8, 4), 0), ((8, 8, 8), 7), ((8, 8, 4), 3),
+                    ((8, 8, 8), 1), ((8, 8, 4), 1000)],
+                1: [((8, 8, 4), 0), ((8, 8, 4), 5), ((8, 8, 4), 1), ((8, 8, 4), 1000)]}
+    for waves, shapes in families.items():
         for arith in (Z.ARITH_FP64, Z.ARITH_FP32):
-            base = ref if arith == Z.ARITH_FP64 else ref32
-            plan = Z.plan_for(bt, arith)
-            plan.set_launch(0, 0, 0, tile, pers, waves)
-            assert np.array_equal(gpu_rhs(bt, plan=plan), base), (tile, pers, waves, arith)
-            out, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, plan=plan)
-            base_stage = stage_ref if arith == Z.ARITH_FP64 else stage_ref32
-            assert np.array_equal(out, base_stage), (tile, pers, waves, arith)
+            ref = stage_ref = None
+            for tile, pers in shapes:
+                plan = _launch_plan(bt, arith, tile, pers, waves)
+                r = gpu_rhs(bt, plan=plan)
+                out, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u, plan=plan)
+                if ref is None:
+                    ref, stage_ref = r, out
+                    continue
+                assert np.array_equal(r, ref), (tile, pers, waves, arith)
+                assert np.array_equal(out, stage_ref), (tile, pers, waves, arith)
+
+
+@pytest.mark.parametrize("seed", [3, 17, 29])
+def test_one_wave_variant_parity(seed):
+    """The one-wave-per-SIMD kernels (two-pass mixed derivatives) against the
+    oracle: right-hand side and a stage increment, FP64; flat space stays
+    exactly zero in both arithmetic types."""
+    Z = z4c()
+    bt = W.random_batch(seed, nblocks=3, nmax=30, fd_order=6)
+    note(f"one-wave variant seed {seed}: " + ", ".join(f"{b.nx}x{b.ny}x{b.nz}" for b in bt.blocks))
+    g = gpu_rhs(bt, plan=_launch_plan(bt, Z.ARITH_FP64, (8, 8, 4), 0, 1))
+    rows = compare(bt, g, O.rhs(bt), O.rhs(bt, ext=True))
+    assert_parity(rows, f"one-wave {seed} rhs\n" + report(rows))
+    gout, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u,
+                        plan=_launch_plan(bt, Z.ARITH_FP64, (8, 8, 4), 3, 1))
+    o64 = bt.u.copy()
+    o80 = bt.u.copy()
+    O.rk_stage(bt, bt.u, o64, bt.u.copy(), bt.u, ORACLE_RK4[1], 0.01)
+    O.rk_stage(bt, bt.u, o80, bt.u.copy(), bt.u, ORACLE_RK4[1], 0.01, ext=True)
+    rows = compare(bt, gout, o64, o80, base=bt.u)
+    assert_parity(rows, f"one-wave {seed} stage\n" + report(rows))
+    flat = W.Batch([W.Block(9, 17, 6, 4, 0.1, 0.2, 0.3), W.Block(16, 16, 16, 4, 0.05, 0.05, 0.05)],
+                   with_matter=False)
+    W.fill_fields(flat, W.flat)
+    flat.params = W.Params(fd_order=6, ko_sigma=0.5)
+    for arith in (Z.ARITH_FP64, Z.ARITH_FP32):
+        assert np.all(gpu_rhs(flat, plan=_launch_plan(flat, arith, (8, 8, 4), 0, 1)) == 0.0)
 
 
 # --- level sets at full size (sampled oracle) -------------------------------------------
