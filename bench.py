@@ -28,11 +28,27 @@ sys.path.insert(0, ROOT)
 METRIC = "Z4c RHS+RK grid-point updates/sec (FP64 vs FP32, batched) + % FP64/HBM roofline"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# FP64 operations executed per interior point and RK stage by the one-wave
+# stage kernel (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 per wave, one
+# point per lane; an FMA counts two)
+FLOP_PER_PT_STAGE = 1844 + 887 + 2 * 1324 + 6
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic HBM bytes per interior point for each RK4 stage (22 FP64 fields,
 # each value moved once): stage 1 reads u0, writes u1 and u0'; stages 2-3 read
 # u0, u1, u2 and write u1, u0'; stage 4 reads u0, u1 and writes u0'.
 STAGE_BYTES = [3 * 176, 5 * 176, 5 * 176, 3 * 176]
+# HBM traffic of one RK4 stage-2 launch (the dominant launch: stages 2 and 3
+# move the most data), from rocprofv3 counter runs of `bench.py --profile`:
+# FETCH_SIZE and WRITE_SIZE summed over the launch's dispatches, each scaled
+# by what the counter reads for a device copy of 1 GiB (FETCH_SIZE reads half
+# the bytes, WRITE_SIZE all of them).  Valid only for the launch shapes and
+# kernels it was taken with; otherwise the benchmark reports null.
+PROFILED_STAGE2 = {
+    "launch_shapes": {8: ((8, 8, 4), 0, 1), 16: ((8, 8, 4), 0, 1), 24: ((8, 8, 4), 0, 1),
+                      32: ((8, 8, 4), 0, 1)},
+    "fetch_kib": 3804519.6, "fetch_scale": 2.0,
+    "write_kib": 2652090.6, "write_scale": 1.0,
+}
 
 
 def log(msg):
@@ -48,7 +64,11 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
-    ap.add_argument("--cpu-sample-blocks", type=int, default=192)
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection run: a 1 GiB device copy (calibration), then "
+                         "--steps launches of RK4 stage 2 in the autotuned configuration")
+    ap.add_argument("--cpu-sample-blocks", type=int, default=0,
+                    help="oracle sample size (0: the whole level set)")
     return ap.parse_args()
 
 
@@ -67,6 +87,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.profile:
+        profile_run(args.steps, stream)
+        return
 
     t0 = time.time()
     bt = W.config4()
@@ -143,9 +166,14 @@ def main():
 
     r64 = results["fp64"]
     value = n_int * nstages / (r64["ms"] * 1e-3)
-    # roofline of the fused stage kernel (algorithmic bytes over its measured duration)
-    bytes_step = n_int * sum(STAGE_BYTES)
-    achieved_gbs = bytes_step / (r64["stage_ms"].sum() * 1e-3) / 1e9
+    # roofline of the dominant launch, a fused RHS + RK4 stage-2 launch:
+    # algorithmic bytes (u0, u1, u2 read; u1, u0' written) over its duration
+    achieved_gbs = n_int * STAGE_BYTES[1] / (r64["stage_ms"][1] * 1e-3) / 1e9
+    step_gbs = n_int * sum(STAGE_BYTES) / (r64["stage_ms"].sum() * 1e-3) / 1e9
+    traffic = None
+    if r64["launches"] == PROFILED_STAGE2["launch_shapes"]:
+        traffic = 1024.0 * (PROFILED_STAGE2["fetch_kib"] * PROFILED_STAGE2["fetch_scale"]
+                            + PROFILED_STAGE2["write_kib"] * PROFILED_STAGE2["write_scale"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -178,8 +206,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "launch": "one fused RHS+RK4 stage-2 launch over all 1024 blocks, "
+                      f"{STAGE_BYTES[1]} algorithmic B per interior point",
         },
+        "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
+        "fp64_flop_per_pt_stage": FLOP_PER_PT_STAGE,
+        "fp64_alu_frac": value * FLOP_PER_PT_STAGE / (FP64_PEAK_TFLOPS * 1e12),
     }
     if "fp32" in results:
         r32 = results["fp32"]
@@ -192,6 +225,37 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
+
+
+def profile_run(launches, stream):
+    """What the committed counter profiles ran: a device copy of 2^27 doubles
+    (1 GiB read, 1 GiB written) to calibrate FETCH_SIZE / WRITE_SIZE, then RK4
+    stage 2 (reads u0, u1, u2; writes u1, u0') of the uneven level set with
+    ghosts read through the periodic rule, in the autotuned launch shapes."""
+    import torch
+
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    bt = W.config4()
+    plan = Z.plan_for(bt, Z.ARITH_FP64)
+    u = torch.from_numpy(bt.u).to("cuda:0")
+    regs = [u.clone(), u.clone(), u.clone(), u.clone()]
+    plan.ghost_fill(Z.GHOST_PERIODIC, regs[0], stream=stream)
+    plan.set_halo(Z.GHOST_PERIODIC)
+    plan.autotune(regs[0], regs[1], regs[3], None, reps=3, stream=stream)
+    torch.cuda.synchronize()
+    shapes = {s: plan.get_launch(s, s, s) for s in (8, 16, 24, 32)}
+    log(f"[profile] launch shapes {shapes}; {launches} launches of RK4 stage 2")
+    for _ in range(launches):
+        plan.rk_stage(regs[0], regs[1], regs[3], regs[2], None, Z.RK4[1], bt.dt, stream=stream)
+    torch.cuda.synchronize()
+    log("[profile] done")
 
 
 def batching(stream, reps):
@@ -267,9 +331,14 @@ def cpu_baseline(bt, nsample):
     O.build(force=False)
     rng = np.random.default_rng(7)
     sizes = np.array([b.nx for b in bt.blocks])
-    per = max(1, nsample // 4)
-    idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0], size=per, replace=False)
-                          for s in (8, 16, 24, 32)])
+    if nsample <= 0 or nsample >= len(bt.blocks):
+        idx = np.arange(len(bt.blocks))
+    else:
+        # the same share of every size class
+        idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0],
+                                         size=max(1, round(nsample * np.count_nonzero(sizes == s)
+                                                           / len(bt.blocks))), replace=False)
+                              for s in (8, 16, 24, 32)])
     sub = bt.subset(idx)
     O.ghost_fill(sub, sub.u)
     t0 = time.time()
@@ -277,9 +346,9 @@ def cpu_baseline(bt, nsample):
     dt = time.time() - t0
     pts = sub.ninterior * 4
     return {"value": pts / dt, "unit": "pt-stage/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"one RK4 step (4 stages + periodic ghost refresh) of {len(idx)} blocks "
-                      f"({per} of each size 8/16/24/32^3, {sub.ninterior} interior points) of "
-                      f"the same level set, {dt:.1f} s"}
+            "sample": f"one RK4 step (4 stages + periodic ghost refresh) of {len(idx)} of the "
+                      f"{len(bt.blocks)} blocks ({sub.ninterior} interior points) of the same "
+                      f"level set, {dt:.1f} s"}
 
 
 if __name__ == "__main__":
