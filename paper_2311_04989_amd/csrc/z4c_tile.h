@@ -567,9 +567,7 @@ __device__ __forceinline__ double &at(double *b, unsigned boff)
 // from the array base.  Elements beyond the stored region of the block
 // (ragged tiles) are clamped to an in-bounds point: no active point's
 // stencil reaches them.
-// REG: sources and LDS destinations held in registers (one wave per SIMD,
-// where registers are plentiful) instead of LDS / recomputed.
-template <int NLD, int NT, int LX, int LY, int LZ, int PX, int PXY, bool GEN, bool REG = false>
+template <int NLD, int NT, int LX, int LY, int LZ, int PX, int PXY, bool GEN>
 struct LStager {
     static constexpr int LVOL = LX * LY * LZ;
     double pf[NLD];
@@ -577,16 +575,6 @@ struct LStager {
     long long fs;
     const unsigned *src;                    // LDS, src[q * NT + t]
     unsigned frz, far;                      // bit q: from `frozen` / from another block
-    unsigned rsrc[REG ? NLD : 1];
-    int rdst[REG ? NLD : 1];
-
-    __device__ __forceinline__ unsigned source(int q, int t) const
-    {
-        if constexpr (REG)
-            return rsrc[q];
-        else
-            return src[q * NT + t];
-    }
 
     __device__ __forceinline__ void prefetch(int f, int t)
     {
@@ -595,7 +583,7 @@ struct LStager {
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             if ((q + 1) * NT <= LVOL || t + q * NT < LVOL) {
-                const unsigned o = source(q, t);
+                const unsigned o = src[q * NT + t];
                 if (GEN && ((sp >> q) & 1u)) {
                     pf[q] = (far >> q) & 1u ? (all + (long long)f * fs)[o]
                                             : at(own_frozen + (long long)f * fs, o);
@@ -612,12 +600,8 @@ struct LStager {
         for (int q = 0; q < NLD; ++q) {
             const int e = t + q * NT;
             if ((q + 1) * NT <= LVOL || e < LVOL) {
-                if constexpr (REG) {
-                    lds[rdst[q]] = pf[q];
-                } else {
-                    const int lx = e % LX, r1 = e / LX, ly = r1 % LY, lz = r1 / LY;
-                    lds[lz * PXY + ly * PX + lx] = pf[q];
-                }
+                const int lx = e % LX, r1 = e / LX, ly = r1 % LY, lz = r1 / LY;
+                lds[lz * PXY + ly * PX + lx] = pf[q];
             }
         }
     }
@@ -625,8 +609,8 @@ struct LStager {
 
 // GEN: sources may be frozen or other blocks' points (frozen and neighbour
 // rules); otherwise every source is a point of the block itself.
-template <int NLD, int NT, int RAD, int LX, int LY, int LZ, int PX, int PXY, bool GEN, bool REG>
-__device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN, REG> &st,
+template <int NLD, int NT, int RAD, int LX, int LY, int LZ, int PX, int PXY, bool GEN>
+__device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> &st,
                                               unsigned *src, const StageArgs &a, const Tile &T,
                                               const z4c_block &B, int t)
 {
@@ -675,12 +659,7 @@ __device__ __forceinline__ void setup_lstager(LStager<NLD, NT, LX, LY, LZ, PX, P
                     st.frz |= 1u << q;
                 }   // else: the stored ghost, which a refresh leaves as it is
             }
-            if constexpr (REG) {
-                st.rsrc[q] = w;
-                st.rdst[q] = lz * PXY + ly * PX + lx;
-            } else {
-                src[q * NT + t] = w;
-            }
+            src[q * NT + t] = w;
         }
     }
 }
@@ -1126,7 +1105,6 @@ stage_kernel(const StageArgs a)
     constexpr bool CHAIN = WPE > 1;
     // one workgroup per CU: LDS for the two-pass mixed derivatives
     constexpr bool MIX2 = WPE == 1;
-    constexpr bool SREG = WPE == 1;   // stager sources and destinations in registers
     using MD = MixDims<P, TX, TY, TZ>;
     __shared__ double lds[PXY * LZ];
     __shared__ R dxb[MIX2 ? MD::NXS : 1];
@@ -1137,9 +1115,9 @@ stage_kernel(const StageArgs a)
     // the shift stage to the At stage).  Each slot is one R per thread,
     // consecutive threads adjacent.
     constexpr int WG_PER_CU = (4 * WPE * 64 + NT - 1) / NT;
-    __shared__ unsigned src_lds[SREG ? 1 : NLD * NT];
+    __shared__ unsigned src_lds[NLD * NT];
     constexpr int SLOT_BUDGET =
-        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - (SREG ? 0 : NLD * NT * 4)
+        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4
          - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)) / (NT * (int)sizeof(R));
     constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
     constexpr bool DB_SLOT = SLOT_BUDGET >= (GU_SLOT ? 27 : 9);
@@ -1176,8 +1154,8 @@ stage_kernel(const StageArgs a)
         const double *ub = a.u + B.offset;
         const long long fs = B.field_stride;
 
-        LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN, SREG> st;
-        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN, SREG>(st, src_lds, a, T, B, t);
+        LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> st;
+        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN>(st, src_lds, a, T, B, t);
         auto stage = [&](auto FC) __attribute__((always_inline)) {
             constexpr int NX = next_field<MODE>(decltype(FC)::value);
             __syncthreads();
