@@ -69,6 +69,10 @@ def parse():
                          "--steps launches of RK4 stage 2 in the autotuned configuration")
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="oracle sample size (0: the whole level set)")
+    ap.add_argument("--table", action="store_true",
+                    help="instead of the benchmark line: GPU FP64 / FP32 throughput of every "
+                         "workload configuration and the oracle on 1 and on all host threads "
+                         "(configurations 2-4), one JSON line")
     return ap.parse_args()
 
 
@@ -89,6 +93,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile:
         profile_run(args.steps, stream)
+        return
+    if args.table:
+        print(json.dumps(config_table(stream, max(args.steps, 20), args.warmup)), flush=True)
         return
 
     t0 = time.time()
@@ -319,6 +326,130 @@ def batching(stream, reps):
         p.close()
     plan.close()
     return res
+
+
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+def config_table(stream, reps, warmup):
+    """Every workload configuration on the GPU, FP64 and FP32 arithmetic,
+    (median, min) ms over `reps` timed repetitions after `warmup`:
+    1: one RK4 step (4 fused stages + periodic ghost refreshes) in a graph;
+    2: one RHS and one RK4 stage-2 launch (reads u0, u1, u2);
+    3: one RK4 stage-2 launch over the 512 blocks;
+    4: one RK4 step, ghosts read through the periodic rule, in a graph;
+    5: one RK4 step (neighbour copies + frozen outer ghosts) in a graph.
+    The oracle (FP64, host) times one RK4 stage 2 on configurations 2-4,
+    on one thread (a seeded sample of blocks for 3 and 4) and on all threads."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    def dev(a):
+        return None if a is None else torch.from_numpy(a).to("cuda:0")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), float(np.min(ms))
+
+    rows = {}
+    nall = None
+    for c in (1, 2, 3, 4, 5):
+        t0 = time.time()
+        bt = W.CONFIGS[c]()
+        log(f"[table] config {c}: {bt.name}, {bt.ninterior} interior points "
+            f"(generated in {time.time() - t0:.1f} s)")
+        row = {"workload": bt.name, "interior_points": bt.ninterior}
+        u, m, fz = dev(bt.u), dev(bt.matter), dev(bt.frozen)
+        for arith, label in ((Z.ARITH_FP64, "fp64"), (Z.ARITH_FP32, "fp32")):
+            plan = Z.plan_for(bt, arith)
+            regs = [u.clone(), u.clone(), u.clone(), torch.zeros_like(u)]
+            if c == 4:
+                plan.ghost_fill(Z.GHOST_PERIODIC, regs[0], stream=stream)
+                plan.set_halo(Z.GHOST_PERIODIC)
+            plan.autotune(regs[0], regs[1], regs[3], m, reps=3, stream=stream)
+            if c in (1, 4, 5):
+                flags = Z.STEP_NO_FINAL_FILL if c == 4 else 0
+
+                def step():
+                    plan.step(regs, m, Z.RK4, bt.dt, bt.ghost, fz, stream=stream, graph=True,
+                              flags=flags)
+                med, mn = timed(step)
+                row[label] = {"what": "RK4 step", "ms": (med, mn),
+                              "pt_stage_per_s": 4 * bt.ninterior / (med * 1e-3)}
+            else:
+                def stage():
+                    plan.rk_stage(regs[0], regs[1], regs[3], regs[2], m, Z.RK4[1], bt.dt,
+                                  stream=stream)
+                med, mn = timed(stage)
+                row[label] = {"what": "RK4 stage 2", "ms": (med, mn),
+                              "pt_stage_per_s": bt.ninterior / (med * 1e-3)}
+                if c == 2:
+                    out = torch.zeros_like(u)
+                    rmed, rmn = timed(lambda: plan.rhs(regs[0], m, out, stream=stream))
+                    row[label]["rhs_ms"] = (rmed, rmn)
+                    row[label]["rhs_pt_per_s"] = bt.ninterior / (rmed * 1e-3)
+            row[label]["nonfinite"] = plan.check_finite(regs[0], stream=stream)
+            log(f"[table] config {c} {label}: {row[label]}")
+            del regs
+            plan.close()
+        del u, m, fz
+        torch.cuda.empty_cache()
+        if c in (2, 3, 4):
+            O.build(force=False)
+            if nall is None:
+                nall = O.max_threads()   # before any call sets a thread count
+            row["oracle"] = {}
+            rng = np.random.default_rng(11)
+            for nthr, key in ((1, "1_thread"), (0, "all_threads")):
+                if nthr == 1 and len(bt.blocks) > 1:
+                    # a seeded sample of about 1/16 of the blocks, every size class
+                    sizes = np.array([b.nx for b in bt.blocks])
+                    idx = np.concatenate([
+                        rng.choice(np.nonzero(sizes == s)[0],
+                                   size=max(1, np.count_nonzero(sizes == s) // 16), replace=False)
+                        for s in np.unique(sizes)])
+                    sub = bt.subset(idx)
+                else:
+                    sub = bt
+                y = sub.u.copy()
+                u1 = sub.u.copy()
+                out = sub.u.copy()
+                t0 = time.time()
+                O.rk_stage(sub, sub.u, out, u1, y, O.RK4[1], sub.dt, nthreads=nthr)
+                dt = time.time() - t0
+                row["oracle"][key] = {"pt_stage_per_s": sub.ninterior / dt, "seconds": dt,
+                                      "interior_points": sub.ninterior,
+                                      "threads": 1 if nthr == 1 else nall}
+            log(f"[table] config {c} oracle: {row['oracle']}")
+        rows[str(c)] = row
+        del bt
+    return {"table": "per-configuration throughput, pt-stage/s", "host": host_info(),
+            "configs": rows}
 
 
 def cpu_baseline(bt, nsample):

@@ -612,11 +612,15 @@ static work_item *make_work(const orc_block *blocks, int nb, long *count)
     return w;
 }
 
+/* nthreads > 0: that many threads; 0: the OpenMP default of the process
+ * (as it was before the first call here). */
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
+    static int default_threads = 0;
+    if (default_threads == 0)
+        default_threads = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : default_threads);
 #else
     (void)nthreads;
 #endif

@@ -52,7 +52,17 @@ def compare(batch, gpu, o64, o80, nfields=W.NF, base=None, blocks=None, names=No
     return rows
 
 
+# (case, worst e_gpu, worst e_fp64_oracle, worst e_gpu / tol) of every
+# comparison made in this process; printed at the end of the test session
+SUMMARY = []
+
+
 def assert_parity(rows, label=""):
+    case = label.split("\n")[0]
+    graded = [(eg, ec, eg / tol) for _, eg, ec, tol, m in rows if m != 0.0]
+    if graded:
+        SUMMARY.append((case, max(g[0] for g in graded), max(g[1] for g in graded),
+                        max(g[2] for g in graded)))
     bad = []
     for name, eg, ec, tol, m in rows:
         if m == 0.0:
