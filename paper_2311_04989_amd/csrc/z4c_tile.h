@@ -437,6 +437,14 @@ __host__ __device__ constexpr int next_field(int f)
     return -1;
 }
 
+// Fields whose u1/u2 values the one-wave stage kernel requests one stage
+// early: every field completed in its own stage (not Gamma-tilde, which is
+// completed after Theta).
+__host__ __device__ constexpr bool early_old(int f)
+{
+    return f >= 0 && !(f >= GAMX && f <= GAMZ);
+}
+
 template <typename R>
 __device__ __forceinline__ Fac<R> load_fac(const StageArgs &a, int block)
 {
@@ -1103,6 +1111,7 @@ stage_kernel(const StageArgs a)
     constexpr int NLD = (LVOL + NT - 1) / NT;
     constexpr bool RK = MODE == MODE_RK;
     constexpr bool CHAIN = WPE > 1;
+    constexpr bool EARLY_OLD = WPE == 1;
     // one workgroup per CU: LDS for the two-pass mixed derivatives
     constexpr bool MIX2 = WPE == 1;
     using MD = MixDims<P, TX, TY, TZ>;
@@ -1154,44 +1163,13 @@ stage_kernel(const StageArgs a)
         const double *ub = a.u + B.offset;
         const long long fs = B.field_stride;
 
-        LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> st;
-        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN>(st, src_lds, a, T, B, t);
-        auto stage = [&](auto FC) __attribute__((always_inline)) {
-            constexpr int NX = next_field<MODE>(decltype(FC)::value);
-            __syncthreads();
-            st.store(lds, t);
-            if constexpr (NX >= 0)
-                st.prefetch(NX, t);
-            __syncthreads();
-            constexpr int FF = decltype(FC)::value;
-            if constexpr (MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
-                                   || (FF >= BETAX && FF <= BETAZ))) {
-                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds, dxb, dyb, t);
-                __syncthreads();
-            }
-            loff = tofs;
-            asm volatile("" : "+v"(loff));
-        };
-        st.prefetch(BETAX, t);
-
-        const Fac<R> F = load_fac<R>(a, T.block);
-        // first and second derivatives and dissipation of the staged field
-        auto derivs2 = [&](R d[3], R dd[6], R &ko) __attribute__((always_inline)) {
-            if constexpr (MIX2)
-                all_ko_sums<P, R, PX, PXY, TX, TY, TZ>(lds, loff, F, d, dd, ko, dxb, dyb, tx, ty,
-                                                       tz);
-            else
-                all_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, dd, ko);
-        };
-        auto centre = [&](int f) __attribute__((always_inline)) {
-            return active ? R(at(ub + f * fs, upt8)) : R(0);
-        };
         double *ob = a.out + B.offset;
         double *u1b = a.u1 ? a.u1 + B.offset : nullptr;
         const double *u2b = a.u2 ? a.u2 + B.offset : nullptr;
         // Values of field f at this point in the u1 and u2 registers, loaded
         // at the start of the stage that completes f so that the stage's LDS
-        // work covers their latency.
+        // work covers their latency; with one wave per SIMD (no other wave to
+        // cover it), one stage before, with the halo prefetch of f.
         struct Old {
             double u1, u2;
         };
@@ -1205,6 +1183,51 @@ stage_kernel(const StageArgs a)
                     o.u2 = at(u2b + e, upt8);
             }
             return o;
+        };
+        Old pending{0.0, 0.0};
+
+        LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> st;
+        setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN>(st, src_lds, a, T, B, t);
+        // Stages field FF; returns the early-loaded u1/u2 values of FF.
+        auto stage = [&](auto FC) __attribute__((always_inline)) {
+            constexpr int FF = decltype(FC)::value;
+            constexpr int NX = next_field<MODE>(FF);
+            __syncthreads();
+            st.store(lds, t);
+            if constexpr (NX >= 0)
+                st.prefetch(NX, t);
+            const Old mine = pending;
+            if constexpr (RK && EARLY_OLD && early_old(NX)) {
+                if (active)
+                    pending = old(NX);
+            }
+            __syncthreads();
+            if constexpr (MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
+                                   || (FF >= BETAX && FF <= BETAZ))) {
+                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds, dxb, dyb, t);
+                __syncthreads();
+            }
+            loff = tofs;
+            asm volatile("" : "+v"(loff));
+            return mine;
+        };
+        st.prefetch(BETAX, t);
+        if constexpr (RK && EARLY_OLD && early_old(BETAX)) {
+            if (active)
+                pending = old(BETAX);
+        }
+
+        const Fac<R> F = load_fac<R>(a, T.block);
+        // first and second derivatives and dissipation of the staged field
+        auto derivs2 = [&](R d[3], R dd[6], R &ko) __attribute__((always_inline)) {
+            if constexpr (MIX2)
+                all_ko_sums<P, R, PX, PXY, TX, TY, TZ>(lds, loff, F, d, dd, ko, dxb, dyb, tx, ty,
+                                                       tz);
+            else
+                all_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, dd, ko);
+        };
+        auto centre = [&](int f) __attribute__((always_inline)) {
+            return active ? R(at(ub + f * fs, upt8)) : R(0);
         };
         // State value of the field staged in LDS at this thread's point.
         auto staged = [&]() __attribute__((always_inline)) { return lds[loff]; };
@@ -1284,9 +1307,9 @@ stage_kernel(const StageArgs a)
         R divb = R(0);
         sfor<3>([&](auto K_c) __attribute__((always_inline)) {
             constexpr int kk = decltype(K_c)::value;
-            stage(std::integral_constant<int, BETAX + kk>{});
+            const Old oe = stage(std::integral_constant<int, BETAX + kk>{});
             if (active) {
-                const Old o = old(BETAX + kk);
+                const Old o = EARLY_OLD && early_old(BETAX + kk) ? oe : old(BETAX + kk);
                 const R Gam = R(at(ub + (GAMX + kk) * fs, upt8));
                 R d[3], dd[6], ko;
                 derivs2(d, dd, ko);
@@ -1314,9 +1337,9 @@ stage_kernel(const StageArgs a)
         sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
             constexpr int ii = SI(q), jj = SJ(q);
-            stage(std::integral_constant<int, GXX + q>{});
+            const Old oe = stage(std::integral_constant<int, GXX + q>{});
             if (active) {
-                const Old o = old(GXX + q);
+                const Old o = EARLY_OLD && early_old(GXX + q) ? oe : old(GXX + q);
                 const R Aq = R(at(ub + (AXX + q) * fs, upt8));
                 R d[3], dd[6], ko;
                 derivs2(d, dd, ko);
@@ -1455,9 +1478,9 @@ stage_kernel(const StageArgs a)
         R dchi[3];
         R PA[6];                      // At source without the D_i D_j alpha term
         R Kpart = R(0), Tpart = R(0); // pointwise sources of Khat (without D^2 alpha), Theta
-        stage(std::integral_constant<int, CHI>{});
+        const Old oe_chi = stage(std::integral_constant<int, CHI>{});
         if (active) {
-            const Old o = old(CHI);
+            const Old o = EARLY_OLD && early_old(CHI) ? oe_chi : old(CHI);
             R A[6];
             sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
                 constexpr int q = decltype(Q_c)::value;
@@ -1568,9 +1591,9 @@ stage_kernel(const StageArgs a)
 
         // ---- lapse: D_i D_j alpha; alpha is complete; the lapse terms of
         // the Khat and At sources
-        stage(std::integral_constant<int, ALPHA>{});
+        const Old oe_alpha = stage(std::integral_constant<int, ALPHA>{});
         if (active) {
-            const Old o = old(ALPHA);
+            const Old o = EARLY_OLD && early_old(ALPHA) ? oe_alpha : old(ALPHA);
             R dal[3], dd[6], ko;
             derivs2(dal, dd, ko);
             R ca = R(0);   // gt^{kl} d_k chi d_l alpha
@@ -1620,9 +1643,10 @@ stage_kernel(const StageArgs a)
         Old gamo[3];
         sfor<2>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
-            stage(std::integral_constant<int, q == 0 ? KHAT : THETA>{});
+            const Old oe = stage(std::integral_constant<int, q == 0 ? KHAT : THETA>{});
             if (active) {
-                const Old o = old(q == 0 ? KHAT : THETA);
+                const Old o = EARLY_OLD && early_old(q == 0 ? KHAT : THETA) ? oe
+                                                                             : old(q == 0 ? KHAT : THETA);
                 if constexpr (q == 1 && RK) {
                     sfor<3>([&](auto I_c) __attribute__((always_inline)) {
                         constexpr int ii = decltype(I_c)::value;
@@ -1653,9 +1677,9 @@ stage_kernel(const StageArgs a)
         double vA[6], vn[6];
         sfor<6>([&](auto Q_c) __attribute__((always_inline)) {
             constexpr int q = decltype(Q_c)::value;
-            stage(std::integral_constant<int, AXX + q>{});
+            const Old oe = stage(std::integral_constant<int, AXX + q>{});
             if (active) {
-                const Old o = old(AXX + q);
+                const Old o = EARLY_OLD && early_old(AXX + q) ? oe : old(AXX + q);
                 if constexpr (q == 5 && RK) {
                     // the new conformal metric, as stored by this thread
                     unsigned upr = upt8;
