@@ -471,3 +471,174 @@ def random_batch(seed: int, nblocks: int = 3, nmax: int = 40, ng=None, fd_order=
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
+
+
+# --- matter coupling: vertex-centred Z4c grid, cell-centred fluid grid ------
+
+NGEOM = 7    # CC geometry: chi, gt_xx, gt_xy, gt_xz, gt_yy, gt_yz, gt_zz
+NPRIM = 8    # CC primitives: rho, ut^x, ut^y, ut^z, p, B^x, B^y, B^z
+PRIMS = ["rho", "utx", "uty", "utz", "p", "Bx", "By", "Bz"]
+
+MBLOCK_DTYPE = np.dtype([("vs_offset", np.int64), ("vm_offset", np.int64),
+                         ("vc_stride", np.int64), ("cg_offset", np.int64),
+                         ("cp_offset", np.int64), ("ca_offset", np.int64),
+                         ("cc_stride", np.int64), ("ncx", np.int32), ("ncy", np.int32),
+                         ("ncz", np.int32), ("ngv", np.int32), ("ngc", np.int32),
+                         ("pad", np.int32)])
+
+
+@dataclasses.dataclass
+class MBlock:
+    """One MeshBlock of nc cells (nc + 1 vertices) per direction; vertex i at
+    x0 + i*dx, the centre of cell i at x0 + (i + 1/2)*dx."""
+    ncx: int
+    ncy: int
+    ncz: int
+    ngv: int
+    ngc: int
+    dx: float
+    x0: tuple = (0.0, 0.0, 0.0)
+
+    @property
+    def vshape(self):
+        g = 2 * self.ngv
+        return (self.ncz + 1 + g, self.ncy + 1 + g, self.ncx + 1 + g)
+
+    @property
+    def cshape(self):
+        g = 2 * self.ngc
+        return (self.ncz + g, self.ncy + g, self.ncx + g)
+
+    def vcoords(self):
+        """Coordinates of every stored vertex (ghosts included), (z, y, x) order."""
+        r = [self.x0[d] + (np.arange(n) - self.ngv) * self.dx
+             for d, n in enumerate(self.vshape[::-1])]
+        Z, Y, X = np.meshgrid(r[2], r[1], r[0], indexing="ij")
+        return X, Y, Z
+
+    def ccoords(self):
+        r = [self.x0[d] + (np.arange(n) - self.ngc + 0.5) * self.dx
+             for d, n in enumerate(self.cshape[::-1])]
+        Z, Y, X = np.meshgrid(r[2], r[1], r[0], indexing="ij")
+        return X, Y, Z
+
+
+class MatterBatch:
+    """Blocks with their five arrays: VC state (22 fields), VC matter (10),
+    CC geometry (7), CC primitives (8), CC ADM sources (10); block-major,
+    fields strided by the per-block vertex / cell counts (padded to even)."""
+
+    def __init__(self, blocks: List[MBlock]):
+        self.blocks = list(blocks)
+        vs = np.array([_pad_even(int(np.prod(b.vshape))) for b in self.blocks], dtype=np.int64)
+        cs = np.array([_pad_even(int(np.prod(b.cshape))) for b in self.blocks], dtype=np.int64)
+        vstart = np.concatenate([[0], np.cumsum(vs)])
+        cstart = np.concatenate([[0], np.cumsum(cs)])
+        self.vc_stride, self.cc_stride = vs, cs
+        self.vs_offset, self.vm_offset = NF * vstart[:-1], NM * vstart[:-1]
+        self.cg_offset, self.cp_offset = NGEOM * cstart[:-1], NPRIM * cstart[:-1]
+        self.ca_offset = NM * cstart[:-1]
+        nv, nc = int(vstart[-1]), int(cstart[-1])
+        self.u = np.zeros(NF * nv)
+        self.matter = np.zeros(NM * nv)
+        self.geom = np.zeros(NGEOM * nc)
+        self.prim = np.zeros(NPRIM * nc)
+        self.adm = np.zeros(NM * nc)
+        self.name = ""
+
+    _KIND = {"u": ("vs_offset", "vc_stride", "vshape"), "matter": ("vm_offset", "vc_stride", "vshape"),
+             "geom": ("cg_offset", "cc_stride", "cshape"), "prim": ("cp_offset", "cc_stride", "cshape"),
+             "adm": ("ca_offset", "cc_stride", "cshape")}
+
+    def view(self, kind: str, arr: np.ndarray, b: int, f: int) -> np.ndarray:
+        """Stored (ghosts included) field f of block b of an array of `kind`
+        ("u", "matter", "geom", "prim" or "adm"), indexed [k, j, i]."""
+        off, st, shp = self._KIND[kind]
+        blk = self.blocks[b]
+        shape = getattr(blk, shp)
+        s = int(getattr(self, off)[b] + f * getattr(self, st)[b])
+        return arr[s:s + int(np.prod(shape))].reshape(shape)
+
+    def table(self) -> np.ndarray:
+        t = np.zeros(len(self.blocks), dtype=MBLOCK_DTYPE)
+        for i, b in enumerate(self.blocks):
+            t[i] = (self.vs_offset[i], self.vm_offset[i], self.vc_stride[i], self.cg_offset[i],
+                    self.cp_offset[i], self.ca_offset[i], self.cc_stride[i], b.ncx, b.ncy, b.ncz,
+                    b.ngv, b.ngc, 0)
+        return t
+
+    @property
+    def ncells(self) -> int:
+        return sum(b.ncx * b.ncy * b.ncz for b in self.blocks)
+
+    @property
+    def nvertices(self) -> int:
+        return sum((b.ncx + 1) * (b.ncy + 1) * (b.ncz + 1) for b in self.blocks)
+
+
+def fill_fluid(mb: MatterBatch, rng, K=100.0, gamma_ad=2.0, rho_peak=1e-3, omega=0.02,
+               B0=1e-3, noise=1e-6):
+    """Conformally flat star-like metric (config-2 parameters) with a smooth
+    anisotropic perturbation of gt_ij at the vertices (ghosts included);
+    at the cells: Gaussian density blobs of peak `rho_peak`, polytropic
+    pressure p = K rho^Gamma (the TOV polytrope K = 100, Gamma = 2), a rigid
+    rotation ut = omega (-y, x, 0) plus a seeded vertical velocity, and a
+    smooth tilted magnetic field of strength ~B0 scaled by the density;
+    U(-noise, noise) on every field."""
+    centres = rng.uniform(-4.0, 4.0, size=(4, 3))
+    tilt = rng.normal(size=3)
+    tilt /= np.linalg.norm(tilt)
+    vz = rng.uniform(-0.05, 0.05)
+    for b, blk in enumerate(mb.blocks):
+        X, Y, Z = blk.vcoords()
+        st = star_metric(X, Y, Z)
+        for f in range(NF):
+            mb.view("u", mb.u, b, f)[...] = st[FIELDS[f]]
+        h = 0.02 * np.sin(0.3 * X + 0.2 * Y) * np.cos(0.25 * Z)
+        for q, (i, j) in enumerate(SYM):
+            v = mb.view("u", mb.u, b, 1 + q)
+            v += h * (1.0 if i == j else 0.5) * (1 + q) / 6.0
+        for f in range(NF):
+            v = mb.view("u", mb.u, b, f)
+            v += rng.uniform(-noise, noise, size=v.shape)
+        X, Y, Z = blk.ccoords()
+        rho = np.zeros_like(X)
+        for c in centres:
+            rho += rho_peak * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / 8.0)
+        shape = 1.0 + rho / rho_peak
+        vals = [rho, -omega * Y, omega * X, vz * np.ones_like(X), K * rho ** gamma_ad,
+                B0 * tilt[0] * shape, B0 * tilt[1] * shape, B0 * tilt[2] * shape + 0.2 * B0 * np.sin(0.3 * X)]
+        for f in range(NPRIM):
+            v = mb.view("prim", mb.prim, b, f)
+            v[...] = vals[f] + rng.uniform(-noise, noise, size=v.shape) * (rho_peak if f in (0, 4) else 1.0)
+        np.maximum(mb.view("prim", mb.prim, b, 0), 0.0, out=mb.view("prim", mb.prim, b, 0))
+        np.maximum(mb.view("prim", mb.prim, b, 4), 0.0, out=mb.view("prim", mb.prim, b, 4))
+
+
+def matter_level_set(seed_offset: int = 6, nc: int = 128, ngv: int = 4, ngc: int = 3) -> MatterBatch:
+    """Matter coupling on the precision-study level set: 2x2x2 blocks of nc^3
+    cells ((nc+1)^3 vertices) tiling [-16, 16]^3, 4 ghost vertices, 3 ghost
+    cells."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    dx = 16.0 / nc
+    blocks = [MBlock(nc, nc, nc, ngv, ngc, dx, (-16.0 + 16.0 * bx, -16.0 + 16.0 * by, -16.0 + 16.0 * bz))
+              for bz in range(2) for by in range(2) for bx in range(2)]
+    mb = MatterBatch(blocks)
+    fill_fluid(mb, rng)
+    mb.name = f"matter coupling 8x{nc}^3 cells, {ngv} ghost vertices, {ngc} ghost cells"
+    return mb
+
+
+def random_matter_batch(seed: int, nblocks: int = 3, nmax: int = 24, ngv: int = 4,
+                        ngc: int = 3) -> MatterBatch:
+    """Small blocks of seeded uneven cell counts (1 .. nmax per direction)."""
+    rng = np.random.default_rng(SEED_BASE + 1000 + seed)
+    blocks = []
+    for _ in range(nblocks):
+        n = rng.integers(1, nmax + 1, size=3)
+        blocks.append(MBlock(int(n[0]), int(n[1]), int(n[2]), ngv, ngc,
+                             float(rng.uniform(0.2, 1.0)), tuple(rng.uniform(-6.0, 2.0, size=3))))
+    mb = MatterBatch(blocks)
+    fill_fluid(mb, rng, B0=3e-3, omega=0.04)
+    mb.name = f"random matter blocks seed {seed}"
+    return mb
