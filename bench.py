@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-matter", action="store_true",
+                    help="skip the matter-coupling kernels (metric to cells, ADM sources, "
+                         "sources to vertices)")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration), then "
                          "--steps launches of RK4 stage 2 in the autotuned configuration")
@@ -230,6 +233,8 @@ def main():
                        "stage_kernel_ms": r32["stage_ms"].round(4).tolist()}
     if not args.no_batching:
         out["batching"] = batching(stream, args.steps)
+    if not args.no_matter:
+        out["matter_coupling"] = matter_coupling(stream, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
@@ -325,6 +330,70 @@ def batching(stream, reps):
     log(f"[bench] batching: {res}")
     for p in singles:
         p.close()
+    plan.close()
+    return res
+
+
+def matter_coupling(stream, reps):
+    """The matter coupling on the level set of 8 blocks of 128^3 cells (129^3
+    vertices, 4 ghost vertices, 3 ghost cells): chi and gt_ij to the cells and
+    their three ghost layers (order 4), GRMHD ADM sources there, sources back
+    to the vertices (order 6).  Each launch timed alone (median, min of
+    `reps`), and the three in sequence; HBM roofline of each from its
+    algorithmic bytes (every input value read once, every output written
+    once)."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    t0 = time.time()
+    mb = W.matter_level_set()
+    log(f"[bench] matter coupling: generated {mb.name} in {time.time() - t0:.1f}s")
+    plan = Z.mplan_for(mb)
+    dev = lambda a: torch.from_numpy(a).to("cuda:0")   # noqa: E731
+    u, prim = dev(mb.u), dev(mb.prim)
+    geom, adm = torch.zeros(mb.geom.size, dtype=torch.float64, device="cuda:0"), \
+        torch.zeros(mb.adm.size, dtype=torch.float64, device="cuda:0")
+    matter = torch.zeros(mb.matter.size, dtype=torch.float64, device="cuda:0")
+    calls = {
+        "metric_to_cc": lambda: plan.metric_to_cc(4, 3, u, geom, stream=stream),
+        "adm_sources": lambda: plan.adm_sources(1, 2.0, 1e-6, 3, geom, prim, adm, stream=stream),
+        "sources_to_vc": lambda: plan.sources_to_vc(6, adm, matter, stream=stream),
+    }
+    nvs = sum(int(np.prod(b.vshape)) for b in mb.blocks)              # stored vertices
+    ncs = sum(int(np.prod(b.cshape)) for b in mb.blocks)              # stored cells
+    nv = mb.nvertices
+    algo = {"metric_to_cc": 8 * (7 * nvs + 7 * ncs),                  # every stored vertex read
+            "adm_sources": 8 * (7 + 8 + 10) * ncs,
+            "sources_to_vc": 8 * (10 * ncs + 10 * nv)}
+    res = {"workload": mb.name + "; metric order 4 to the cells and 3 ghost layers, GRMHD "
+                                 "sources (Gamma = 2), sources order 6 to the vertices",
+           "cells": mb.ncells, "vertices": nv}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), float(np.min(ms))
+
+    for name, fn in calls.items():
+        med, mn = timed(fn)
+        gbs = algo[name] / (med * 1e-3) / 1e9
+        res[name] = {"ms": (med, mn), "algorithmic_bytes": algo[name], "achieved_gbs": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS}
+    med, mn = timed(lambda: [fn() for fn in calls.values()])
+    res["chain"] = {"ms": (med, mn), "vertices_per_s": nv / (med * 1e-3),
+                    "hbm_frac": sum(algo.values()) / (med * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] matter coupling: {res}")
     plan.close()
     return res
 

@@ -540,6 +540,9 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
 
 }  // namespace
 
+z4c_status z4c::set_error(z4c_status s, const char *msg) { return fail(s, msg); }
+z4c_status z4c::set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
 extern "C" {
 
 const char *z4c_strerror(z4c_status s)

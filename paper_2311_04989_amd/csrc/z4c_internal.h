@@ -92,4 +92,9 @@ hipError_t launch_finite_count(const z4c_block *blocks, int nblocks, const long 
                                unsigned long long *count, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 
+// Last-error message of the calling thread (z4c_last_error), for the host
+// code of every translation unit; both return their status argument.
+z4c_status set_error(z4c_status s, const char *msg);
+z4c_status set_hip_error(hipError_t e, const char *what);
+
 }  // namespace z4c

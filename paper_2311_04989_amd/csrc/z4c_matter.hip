@@ -1,0 +1,444 @@
+// z4c_matter.hip -- matter coupling of the Z4c right-hand side: Lagrange
+// interpolation between the vertex-centred Z4c grid and the cell-centred
+// fluid grid (Sec. 3.2, intergrid communication) and the ADM projections of
+// the perfect-fluid / ideal-GRMHD stress-energy tensor (Sec. 2.1, 2.2).
+//
+// Both kernels work on tiles of MTX x MTY x MTZ output points of one block,
+// one workgroup of 256 threads per tile (x fastest: every row of 16 doubles
+// is one 128-byte request).  Interpolation is separable: the input box of the
+// tile for one field is staged in LDS, then reduced along x, y and z in three
+// passes (3 * order multiply-adds per output instead of order^3), one field
+// after the other.  Both kernels are HBM-bound.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "z4c_internal.h"
+#include "z4c_matter.h"
+
+struct z4c_mplan {
+    std::vector<z4c_mblock> blocks;
+    bool device = false;
+    z4c_mblock *blocks_d = nullptr;
+    void *cc_tiles_d = nullptr;   // MTile[n_cc]: tiles over every stored cell
+    void *vc_tiles_d = nullptr;   // MTile[n_vc]: tiles over vertices [0, nc]
+    int n_cc = 0, n_vc = 0;
+};
+
+namespace z4c {
+namespace {
+
+constexpr int MTX = 16, MTY = 8, MTZ = 4, MNT = 256;
+constexpr int MOUT = MTX * MTY * MTZ;
+
+struct MTile {
+    int block, i0, j0, k0;   // tile origin (stored CC index, or vertex index)
+};
+
+// Weight k of the Lagrange polynomial through O equally spaced nodes,
+// evaluated midway between the two central nodes.
+template <int O>
+__device__ __forceinline__ constexpr double midw(int k)
+{
+    if constexpr (O == 2)
+        return 0.5;
+    else if constexpr (O == 4)
+        return (k == 0 || k == 3) ? -1.0 / 16.0 : 9.0 / 16.0;
+    else
+        return (k == 0 || k == 5) ? 3.0 / 256.0 : ((k == 1 || k == 4) ? -25.0 / 256.0 : 150.0 / 256.0);
+}
+
+template <int O>
+__device__ __forceinline__ double midsum(const double *c, int st)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < O; ++k)
+        s += midw<O>(k) * c[k * st];
+    return s;
+}
+
+// TO_CC: the 7 conformal-geometry fields of the VC state to cells (stored CC
+// index in [ngc - ext, ngc + nc + ext)); otherwise the 10 ADM fields from the
+// CC sources to vertices [0, nc].
+template <int O, bool TO_CC>
+__global__ void __launch_bounds__(MNT)
+interp_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, const double *in, double *out)
+{
+    constexpr int LX = MTX + O - 1, LY = MTY + O - 1, LZ = MTZ + O - 1;
+    __shared__ double s_in[LX * LY * LZ];
+    __shared__ double s_x[MTX * LY * LZ];
+    __shared__ double s_y[MTX * MTY * LZ];
+    const MTile T = tiles[blockIdx.x];
+    const z4c_mblock B = blocks[T.block];
+    const int n[3] = {B.ncx, B.ncy, B.ncz};
+    const int o[3] = {T.i0, T.j0, T.k0};
+    // per direction: the first valid tile-local output index and one past
+    // the last, and the stored input index of the first stencil point of
+    // tile-local output 0
+    int lo[3], hi[3], in0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if constexpr (TO_CC) {
+            lo[d] = B.ngc - ext - o[d];
+            hi[d] = B.ngc + n[d] + ext - o[d];
+            in0[d] = o[d] - B.ngc - O / 2 + 1 + B.ngv;
+        } else {
+            lo[d] = -o[d];
+            hi[d] = n[d] + 1 - o[d];
+            in0[d] = o[d] - O / 2 + B.ngc;
+        }
+    }
+    if (hi[0] <= 0 || hi[1] <= 0 || hi[2] <= 0 || lo[0] >= MTX || lo[1] >= MTY || lo[2] >= MTZ)
+        return;   // the whole tile lies outside this call's range (uniform)
+    const int isx = TO_CC ? B.ncx + 1 + 2 * B.ngv : B.ncx + 2 * B.ngc;
+    const int isy = TO_CC ? B.ncy + 1 + 2 * B.ngv : B.ncy + 2 * B.ngc;
+    const int isz = TO_CC ? B.ncz + 1 + 2 * B.ngv : B.ncz + 2 * B.ngc;
+    const int osx = TO_CC ? B.ncx + 2 * B.ngc : B.ncx + 1 + 2 * B.ngv;
+    const int osy = TO_CC ? B.ncy + 2 * B.ngc : B.ncy + 1 + 2 * B.ngv;
+    const long long ibase = TO_CC ? B.vs_offset : B.ca_offset;
+    const long long ifs = TO_CC ? B.vc_stride : B.cc_stride;
+    const long long obase = TO_CC ? B.cg_offset : B.vm_offset;
+    const long long ofs = TO_CC ? B.cc_stride : B.vc_stride;
+    // stored output index of tile-local output 0
+    const int out0[3] = {TO_CC ? o[0] : o[0] + B.ngv, TO_CC ? o[1] : o[1] + B.ngv,
+                         TO_CC ? o[2] : o[2] + B.ngv};
+    constexpr int NF = TO_CC ? 7 : 10;
+    const int t = threadIdx.x;
+    for (int f = 0; f < NF; ++f) {
+        const double *src = in + ibase + f * ifs;
+        // input box; positions outside the stored array are clamped into it
+        // (they feed only outputs outside the call's range)
+        for (int e = t; e < LX * LY * LZ; e += MNT) {
+            const int lx = e % LX, r = e / LX, ly = r % LY, lz = r / LY;
+            const int gx = min(max(in0[0] + lx, 0), isx - 1);
+            const int gy = min(max(in0[1] + ly, 0), isy - 1);
+            const int gz = min(max(in0[2] + lz, 0), isz - 1);
+            s_in[e] = src[gx + (long long)isx * (gy + (long long)isy * gz)];
+        }
+        __syncthreads();
+        for (int e = t; e < MTX * LY * LZ; e += MNT) {
+            const int x = e % MTX, r = e / MTX;   // r = ly + LY * lz
+            s_x[e] = midsum<O>(s_in + r * LX + x, 1);
+        }
+        __syncthreads();
+        for (int e = t; e < MTX * MTY * LZ; e += MNT) {
+            const int x = e % MTX, r = e / MTX, y = r % MTY, z = r / MTY;
+            s_y[e] = midsum<O>(s_x + (z * LY + y) * MTX + x, MTX);
+        }
+        __syncthreads();
+        double *dst = out + obase + f * ofs;
+        for (int e = t; e < MOUT; e += MNT) {
+            const int x = e % MTX, r = e / MTX, y = r % MTY, z = r / MTY;
+            if (x >= lo[0] && x < hi[0] && y >= lo[1] && y < hi[1] && z >= lo[2] && z < hi[2]) {
+                const double v = midsum<O>(s_y + (z * MTY + y) * MTX + x, MTX * MTY);
+                dst[(out0[0] + x) + (long long)osx * ((out0[1] + y) + (long long)osy * (out0[2] + z))] = v;
+            }
+        }
+        __syncthreads();   // the LDS boxes are refilled for the next field
+    }
+}
+
+// ADM projections at the cells of one tile (stored CC index in
+// [ngc - ext, ngc + nc + ext)).
+template <bool MHD>
+__global__ void __launch_bounds__(MNT)
+adm_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, double gfac, double chi_floor,
+           const double *geom, const double *prim, double *adm)
+{
+    const MTile T = tiles[blockIdx.x];
+    const z4c_mblock B = blocks[T.block];
+    const int sx = B.ncx + 2 * B.ngc, sy = B.ncy + 2 * B.ngc;
+    const long long fs = B.cc_stride;
+    const int a0 = B.ngc - ext;
+    const int ax = B.ngc + B.ncx + ext, ay = B.ngc + B.ncy + ext, az = B.ngc + B.ncz + ext;
+    for (int e = threadIdx.x; e < MOUT; e += MNT) {
+        const int x = T.i0 + e % MTX, r = e / MTX, y = T.j0 + r % MTY, z = T.k0 + r / MTY;
+        if (x < a0 || y < a0 || z < a0 || x >= ax || y >= ay || z >= az)
+            continue;
+        const long long p = x + (long long)sx * (y + (long long)sy * z);
+        const double *g = geom + B.cg_offset + p;
+        const double *w = prim + B.cp_offset + p;
+        const double chi = g[0];
+        const double ic = 1.0 / (chi > chi_floor ? chi : chi_floor);
+        double gam[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            gam[q] = g[(1 + q) * fs] * ic;
+        const double rho = w[0], ux = w[fs], uy = w[2 * fs], uz = w[3 * fs], pr = w[4 * fs];
+        // ut_i = gamma_ij ut^j
+        const double lx = gam[0] * ux + gam[1] * uy + gam[2] * uz;
+        const double ly = gam[1] * ux + gam[3] * uy + gam[4] * uz;
+        const double lz = gam[2] * ux + gam[4] * uy + gam[5] * uz;
+        const double W = sqrt(1.0 + lx * ux + ly * uy + lz * uz);
+        const double iW = 1.0 / W;
+        const double v[3] = {lx * iW, ly * iW, lz * iW};   // v_i
+        const double rhoh = rho + gfac * pr;
+        double E, P, ab0 = 0.0, b[3] = {0.0, 0.0, 0.0};
+        if constexpr (MHD) {
+            const double Bx = w[5 * fs], By = w[6 * fs], Bz = w[7 * fs];
+            const double Blx = gam[0] * Bx + gam[1] * By + gam[2] * Bz;
+            const double Bly = gam[1] * Bx + gam[3] * By + gam[4] * Bz;
+            const double Blz = gam[2] * Bx + gam[4] * By + gam[5] * Bz;
+            ab0 = W * (Bx * v[0] + By * v[1] + Bz * v[2]);           // alpha b^0
+            const double B2 = Blx * Bx + Bly * By + Blz * Bz;
+            const double b2 = (ab0 * ab0 + B2) * iW * iW;
+            b[0] = Blx * iW + ab0 * v[0];                             // b_i
+            b[1] = Bly * iW + ab0 * v[1];
+            b[2] = Blz * iW + ab0 * v[2];
+            E = (rhoh + b2) * W * W;
+            P = pr + 0.5 * b2;
+        } else {
+            E = rhoh * W * W;
+            P = pr;
+        }
+        double *o = adm + B.ca_offset + p;
+        o[0] = E - P - ab0 * ab0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            o[(1 + i) * fs] = E * v[i] - ab0 * b[i];
+        constexpr int QI[6] = {0, 0, 0, 1, 1, 2}, QJ[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            o[(4 + q) * fs] = E * v[QI[q]] * v[QJ[q]] + P * gam[q] - b[QI[q]] * b[QJ[q]];
+    }
+}
+
+template <bool TO_CC>
+hipError_t launch_interp(int order, const z4c_mplan *P, int ext, const double *in, double *out,
+                         hipStream_t s)
+{
+    const MTile *tiles = (const MTile *)(TO_CC ? P->cc_tiles_d : P->vc_tiles_d);
+    const int n = TO_CC ? P->n_cc : P->n_vc;
+    if (n == 0)
+        return hipSuccess;
+    if (order == 2)
+        interp_kernel<2, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+    else if (order == 4)
+        interp_kernel<4, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+    else
+        interp_kernel<6, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+    return hipGetLastError();
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+z4c_status check_plan(const z4c_mplan *P)
+{
+    if (!P)
+        return set_error(Z4C_EINVAL, "mplan is NULL");
+    if (!P->device)
+        return set_error(Z4C_ENODEV, "mplan was created without a device");
+    return Z4C_OK;
+}
+
+z4c_status check_order(int order)
+{
+    if (order != 2 && order != 4 && order != 6)
+        return set_error(Z4C_EINVAL, "interpolation order must be 2, 4 or 6");
+    return Z4C_OK;
+}
+
+}  // namespace
+}  // namespace z4c
+
+using namespace z4c;
+
+extern "C" {
+
+z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4c_mplan **out)
+{
+    if (!out)
+        return set_error(Z4C_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!blocks || nblocks < 1)
+        return set_error(Z4C_EINVAL, "blocks is NULL or nblocks < 1");
+    if (flags & ~Z4C_PLAN_NO_DEVICE)
+        return set_error(Z4C_EINVAL, "unknown flags");
+    std::vector<MTile> cc, vc;
+    for (int b = 0; b < nblocks; ++b) {
+        const z4c_mblock &B = blocks[b];
+        char buf[160];
+        if (B.ncx < 1 || B.ncy < 1 || B.ncz < 1 || B.ngv < 0 || B.ngc < 0) {
+            snprintf(buf, sizeof buf, "block %d: cells must be >= 1 and ghosts >= 0", b);
+            return set_error(Z4C_EINVAL, buf);
+        }
+        if (B.vs_offset < 0 || B.vm_offset < 0 || B.cg_offset < 0 || B.cp_offset < 0
+            || B.ca_offset < 0 || B.vc_stride < 0 || B.cc_stride < 0) {
+            snprintf(buf, sizeof buf, "block %d: offsets and strides must be >= 0", b);
+            return set_error(Z4C_EINVAL, buf);
+        }
+        const long long nv = (long long)(B.ncx + 1 + 2 * B.ngv) * (B.ncy + 1 + 2 * B.ngv)
+                           * (B.ncz + 1 + 2 * B.ngv);
+        const long long nc = (long long)(B.ncx + 2 * B.ngc) * (B.ncy + 2 * B.ngc)
+                           * (B.ncz + 2 * B.ngc);
+        if (B.vc_stride < nv || B.cc_stride < nc) {
+            snprintf(buf, sizeof buf, "block %d: a field stride is smaller than the stored field", b);
+            return set_error(Z4C_EINVAL, buf);
+        }
+        const int sc[3] = {B.ncx + 2 * B.ngc, B.ncy + 2 * B.ngc, B.ncz + 2 * B.ngc};
+        for (int k = 0; k < sc[2]; k += MTZ)
+            for (int j = 0; j < sc[1]; j += MTY)
+                for (int i = 0; i < sc[0]; i += MTX)
+                    cc.push_back({b, i, j, k});
+        for (int k = 0; k <= B.ncz; k += MTZ)
+            for (int j = 0; j <= B.ncy; j += MTY)
+                for (int i = 0; i <= B.ncx; i += MTX)
+                    vc.push_back({b, i, j, k});
+    }
+    if (cc.size() > (size_t)INT32_MAX || vc.size() > (size_t)INT32_MAX)
+        return set_error(Z4C_EINVAL, "too many tiles");
+    z4c_mplan *P = new z4c_mplan;
+    P->blocks.assign(blocks, blocks + nblocks);
+    P->n_cc = (int)cc.size();
+    P->n_vc = (int)vc.size();
+    if (!(flags & Z4C_PLAN_NO_DEVICE)) {
+        hipError_t e = hipMalloc(&P->blocks_d, sizeof(z4c_mblock) * nblocks);
+        if (e == hipSuccess)
+            e = hipMalloc(&P->cc_tiles_d, sizeof(MTile) * cc.size());
+        if (e == hipSuccess)
+            e = hipMalloc(&P->vc_tiles_d, sizeof(MTile) * vc.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(P->blocks_d, blocks, sizeof(z4c_mblock) * nblocks,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(P->cc_tiles_d, cc.data(), sizeof(MTile) * cc.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(P->vc_tiles_d, vc.data(), sizeof(MTile) * vc.size(),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            z4c_mplan_destroy(P);
+            return e == hipErrorOutOfMemory ? set_error(Z4C_ENOMEM, "hipMalloc(mplan tables)")
+                                            : set_hip_error(e, "mplan tables");
+        }
+        P->device = true;
+    }
+    *out = P;
+    return Z4C_OK;
+}
+
+z4c_status z4c_mplan_destroy(z4c_mplan *P)
+{
+    if (!P)
+        return Z4C_OK;
+    if (P->blocks_d)
+        (void)hipFree(P->blocks_d);
+    if (P->cc_tiles_d)
+        (void)hipFree(P->cc_tiles_d);
+    if (P->vc_tiles_d)
+        (void)hipFree(P->vc_tiles_d);
+    delete P;
+    return Z4C_OK;
+}
+
+z4c_status z4c_metric_to_cc(const z4c_mplan *P, int order, int ext, const double *u,
+                            double *geom, void *stream)
+{
+    z4c_status st;
+    if (!P)
+        return set_error(Z4C_EINVAL, "mplan is NULL");
+    if ((st = check_order(order)) != Z4C_OK)
+        return st;
+    if (!u || !geom)
+        return set_error(Z4C_EINVAL, "u and geom must not be NULL");
+    if ((const void *)u == (const void *)geom)
+        return set_error(Z4C_EINVAL, "geom must not alias u");
+    if (!aligned8(u) || !aligned8(geom))
+        return set_error(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (ext < 0)
+        return set_error(Z4C_EINVAL, "ext must be >= 0");
+    for (size_t b = 0; b < P->blocks.size(); ++b) {
+        const z4c_mblock &B = P->blocks[b];
+        char buf[160];
+        if (ext > B.ngc) {
+            snprintf(buf, sizeof buf, "block %zu: ext %d exceeds the %d stored ghost cells", b, ext,
+                     B.ngc);
+            return set_error(Z4C_EINVAL, buf);
+        }
+        if (B.ngv < order / 2 - 1 + ext) {
+            snprintf(buf, sizeof buf, "block %zu: order %d to %d ghost cells needs %d ghost "
+                     "vertices, %d stored", b, order, ext, order / 2 - 1 + ext, B.ngv);
+            return set_error(Z4C_ENOGHOST, buf);
+        }
+    }
+    if ((st = check_plan(P)) != Z4C_OK)
+        return st;
+    const hipError_t e = launch_interp<true>(order, P, ext, u, geom, (hipStream_t)stream);
+    return e == hipSuccess ? Z4C_OK : set_hip_error(e, "interpolation kernel launch");
+}
+
+z4c_status z4c_sources_to_vc(const z4c_mplan *P, int order, const double *adm, double *matter,
+                             void *stream)
+{
+    z4c_status st;
+    if (!P)
+        return set_error(Z4C_EINVAL, "mplan is NULL");
+    if ((st = check_order(order)) != Z4C_OK)
+        return st;
+    if (!adm || !matter)
+        return set_error(Z4C_EINVAL, "adm and matter must not be NULL");
+    if ((const void *)adm == (const void *)matter)
+        return set_error(Z4C_EINVAL, "matter must not alias adm");
+    if (!aligned8(adm) || !aligned8(matter))
+        return set_error(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    for (size_t b = 0; b < P->blocks.size(); ++b) {
+        const z4c_mblock &B = P->blocks[b];
+        if (B.ngc < order / 2) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "block %zu: order %d needs %d ghost cells, %d stored", b,
+                     order, order / 2, B.ngc);
+            return set_error(Z4C_ENOGHOST, buf);
+        }
+    }
+    if ((st = check_plan(P)) != Z4C_OK)
+        return st;
+    const hipError_t e = launch_interp<false>(order, P, 0, adm, matter, (hipStream_t)stream);
+    return e == hipSuccess ? Z4C_OK : set_hip_error(e, "interpolation kernel launch");
+}
+
+z4c_status z4c_adm_sources(const z4c_mplan *P, const z4c_fluid *fluid, int ext,
+                           const double *geom, const double *prim, double *adm, void *stream)
+{
+    z4c_status st;
+    if (!P)
+        return set_error(Z4C_EINVAL, "mplan is NULL");
+    if (!fluid || !geom || !prim || !adm)
+        return set_error(Z4C_EINVAL, "fluid, geom, prim and adm must not be NULL");
+    if (fluid->mhd != 0 && fluid->mhd != 1)
+        return set_error(Z4C_EINVAL, "mhd must be 0 or 1");
+    if (!(fluid->gamma_ad > 1.0) || !std::isfinite(fluid->gamma_ad))
+        return set_error(Z4C_EINVAL, "gamma_ad must be finite and > 1");
+    if (!(fluid->chi_floor > 0.0) || !std::isfinite(fluid->chi_floor))
+        return set_error(Z4C_EINVAL, "chi_floor must be finite and > 0");
+    if ((const void *)adm == (const void *)geom || (const void *)adm == (const void *)prim)
+        return set_error(Z4C_EINVAL, "adm must not alias geom or prim");
+    if (!aligned8(geom) || !aligned8(prim) || !aligned8(adm))
+        return set_error(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (ext < 0)
+        return set_error(Z4C_EINVAL, "ext must be >= 0");
+    for (size_t b = 0; b < P->blocks.size(); ++b)
+        if (ext > P->blocks[b].ngc) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "block %zu: ext %d exceeds the %d stored ghost cells", b,
+                     ext, P->blocks[b].ngc);
+            return set_error(Z4C_EINVAL, buf);
+        }
+    if ((st = check_plan(P)) != Z4C_OK)
+        return st;
+    if (P->n_cc == 0)
+        return Z4C_OK;
+    const double gfac = fluid->gamma_ad / (fluid->gamma_ad - 1.0);
+    const MTile *tiles = (const MTile *)P->cc_tiles_d;
+    if (fluid->mhd)
+        adm_kernel<true><<<P->n_cc, MNT, 0, (hipStream_t)stream>>>(
+            P->blocks_d, tiles, ext, gfac, fluid->chi_floor, geom, prim, adm);
+    else
+        adm_kernel<false><<<P->n_cc, MNT, 0, (hipStream_t)stream>>>(
+            P->blocks_d, tiles, ext, gfac, fluid->chi_floor, geom, prim, adm);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? Z4C_OK : set_hip_error(e, "ADM source kernel launch");
+}
+
+}  // extern "C"

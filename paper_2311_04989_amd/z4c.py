@@ -69,6 +69,22 @@ SSPRK3 = [(0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0, 0),
           (0.0, 0.0, 2.0 / 3.0, 0.0, 1.0 / 3.0, 2.0 / 3.0, 0, 0)]
 
 
+class MBlock(ctypes.Structure):
+    """z4c_mblock of include/z4c_matter.h."""
+    _fields_ = [("vs_offset", ctypes.c_longlong), ("vm_offset", ctypes.c_longlong),
+                ("vc_stride", ctypes.c_longlong), ("cg_offset", ctypes.c_longlong),
+                ("cp_offset", ctypes.c_longlong), ("ca_offset", ctypes.c_longlong),
+                ("cc_stride", ctypes.c_longlong), ("ncx", ctypes.c_int), ("ncy", ctypes.c_int),
+                ("ncz", ctypes.c_int), ("ngv", ctypes.c_int), ("ngc", ctypes.c_int),
+                ("pad", ctypes.c_int)]
+
+
+class Fluid(ctypes.Structure):
+    """z4c_fluid of include/z4c_matter.h."""
+    _fields_ = [("mhd", ctypes.c_int), ("gamma_ad", ctypes.c_double),
+                ("chi_floor", ctypes.c_double)]
+
+
 class Z4cError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"z4c status {status}: {message}")
@@ -111,6 +127,15 @@ def lib():
         L.z4c_last_error.restype = ctypes.c_char_p
         L.z4c_plan_tiles.argtypes = [vp]
         L.z4c_plan_tiles.restype = ctypes.c_longlong
+        L.z4c_mplan_create.argtypes = [ctypes.POINTER(MBlock), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(vp)]
+        L.z4c_mplan_destroy.argtypes = [vp]
+        L.z4c_metric_to_cc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.z4c_adm_sources.argtypes = [vp, ctypes.POINTER(Fluid), ctypes.c_int, vp, vp, vp, vp]
+        L.z4c_sources_to_vc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        for name in ("z4c_mplan_create", "z4c_mplan_destroy", "z4c_metric_to_cc",
+                     "z4c_adm_sources", "z4c_sources_to_vc"):
+            getattr(L, name).restype = st
         for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params", "z4c_plan_set_halo",
                      "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
                      "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill",
@@ -267,3 +292,50 @@ def plan_for(batch, arith: int = ARITH_FP64, flags: int = 0) -> Plan:
     if batch.neighbours is not None:
         p.set_neighbours(batch.neighbours)
     return p
+
+
+def make_mblocks(table: np.ndarray):
+    """C z4c_mblock array from a structured numpy array with its fields."""
+    arr = (MBlock * len(table))()
+    names = [f[0] for f in MBlock._fields_]
+    for i, r in enumerate(table):
+        arr[i] = MBlock(*[int(r[n]) for n in names])
+    return arr
+
+
+class MPlan:
+    """Matter-coupling plan (z4c_mplan): block table and tile lists on the
+    device for z4c_metric_to_cc, z4c_adm_sources and z4c_sources_to_vc."""
+
+    def __init__(self, table: np.ndarray, flags: int = 0):
+        self._h = ctypes.c_void_p()
+        blocks = make_mblocks(table)
+        _check(lib().z4c_mplan_create(blocks, len(table), flags, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().z4c_mplan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def metric_to_cc(self, order, ext, u, geom, stream=None):
+        _check(lib().z4c_metric_to_cc(self._h, int(order), int(ext), _ptr(u), _ptr(geom),
+                                      _stream(stream)))
+
+    def adm_sources(self, mhd, gamma_ad, chi_floor, ext, geom, prim, adm, stream=None):
+        fl = Fluid(int(mhd), float(gamma_ad), float(chi_floor))
+        _check(lib().z4c_adm_sources(self._h, ctypes.byref(fl), int(ext), _ptr(geom), _ptr(prim),
+                                     _ptr(adm), _stream(stream)))
+
+    def sources_to_vc(self, order, adm, matter, stream=None):
+        _check(lib().z4c_sources_to_vc(self._h, int(order), _ptr(adm), _ptr(matter),
+                                       _stream(stream)))
+
+
+def mplan_for(mbatch, flags: int = 0) -> MPlan:
+    return MPlan(mbatch.table(), flags)
