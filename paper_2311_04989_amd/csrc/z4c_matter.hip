@@ -3,12 +3,15 @@
 // fluid grid (Sec. 3.2, intergrid communication) and the ADM projections of
 // the perfect-fluid / ideal-GRMHD stress-energy tensor (Sec. 2.1, 2.2).
 //
-// Both kernels work on tiles of MTX x MTY x MTZ output points of one block,
-// one workgroup of 256 threads per tile (x fastest: every row of 16 doubles
-// is one 128-byte request).  Interpolation is separable: the input box of the
-// tile for one field is staged in LDS, then reduced along x, y and z in three
-// passes (3 * order multiply-adds per output instead of order^3), one field
-// after the other.  Both kernels are HBM-bound.
+// Interpolation is separable and marches along z: a workgroup of 256
+// threads owns a 16 x 16 column of outputs and ITZ output planes; for each
+// input plane it stages the (16 + order - 1)^2 inputs in LDS (the next plane
+// already in flight in registers), reduces them along x and then y, and each
+// thread keeps the y-reduced values of the last `order` planes in registers
+// for the z reduction, so every input plane is read once per column and the
+// z halo costs (order - 1) / ITZ extra planes.  The ADM projections are
+// pointwise, one cell per thread.  Both kernels are HBM-bound; every row of
+// 16 doubles is one 128-byte request.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -21,16 +24,19 @@ struct z4c_mplan {
     std::vector<z4c_mblock> blocks;
     bool device = false;
     z4c_mblock *blocks_d = nullptr;
-    void *cc_tiles_d = nullptr;   // MTile[n_cc]: tiles over every stored cell
-    void *vc_tiles_d = nullptr;   // MTile[n_vc]: tiles over vertices [0, nc]
-    int n_cc = 0, n_vc = 0;
+    void *cc_tiles_d = nullptr;   // MTile[n_cc]: interpolation columns over every stored cell
+    void *vc_tiles_d = nullptr;   // MTile[n_vc]: interpolation columns over vertices [0, nc]
+    void *pt_tiles_d = nullptr;   // MTile[n_pt]: point tiles over every stored cell
+    int n_cc = 0, n_vc = 0, n_pt = 0;
 };
 
 namespace z4c {
 namespace {
 
-constexpr int MTX = 16, MTY = 8, MTZ = 4, MNT = 256;
-constexpr int MOUT = MTX * MTY * MTZ;
+// interpolation columns: ITX x ITY outputs per plane, ITZ planes, one thread per (x, y)
+constexpr int ITX = 16, ITY = 16, ITZ = 16, INT_ = ITX * ITY;
+// point tiles of the ADM projections: one cell per thread
+constexpr int PTX = 16, PTY = 8, PTZ = 4, PNT = PTX * PTY * PTZ;
 
 struct MTile {
     int block, i0, j0, k0;   // tile origin (stored CC index, or vertex index)
@@ -63,17 +69,20 @@ __device__ __forceinline__ double midsum(const double *c, int st)
 // index in [ngc - ext, ngc + nc + ext)); otherwise the 10 ADM fields from the
 // CC sources to vertices [0, nc].
 template <int O, bool TO_CC>
-__global__ void __launch_bounds__(MNT)
+__global__ void __launch_bounds__(INT_)
 interp_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, const double *in, double *out)
 {
-    constexpr int LX = MTX + O - 1, LY = MTY + O - 1, LZ = MTZ + O - 1;
-    __shared__ double s_in[LX * LY * LZ];
-    __shared__ double s_x[MTX * LY * LZ];
-    __shared__ double s_y[MTX * MTY * LZ];
+    constexpr int LX = ITX + O - 1, LY = ITY + O - 1;
+    constexpr int NPL = LX * LY;                      // one input plane
+    constexpr int NLD = (NPL + INT_ - 1) / INT_;      // its values per thread
+    constexpr int NP = ITZ + O - 1;                   // input planes per column
+    __shared__ double s_pl[NPL];
+    __shared__ double s_x[ITX * LY];
     const MTile T = tiles[blockIdx.x];
     const z4c_mblock B = blocks[T.block];
     const int n[3] = {B.ncx, B.ncy, B.ncz};
     const int o[3] = {T.i0, T.j0, T.k0};
+    constexpr int TD[3] = {ITX, ITY, ITZ};
     // per direction: the first valid tile-local output index and one past
     // the last, and the stored input index of the first stencil point of
     // tile-local output 0
@@ -90,8 +99,9 @@ interp_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, const doubl
             in0[d] = o[d] - O / 2 + B.ngc;
         }
     }
-    if (hi[0] <= 0 || hi[1] <= 0 || hi[2] <= 0 || lo[0] >= MTX || lo[1] >= MTY || lo[2] >= MTZ)
-        return;   // the whole tile lies outside this call's range (uniform)
+    if (hi[0] <= 0 || hi[1] <= 0 || hi[2] <= 0 || lo[0] >= TD[0] || lo[1] >= TD[1]
+        || lo[2] >= TD[2])
+        return;   // the whole column lies outside this call's range (uniform)
     const int isx = TO_CC ? B.ncx + 1 + 2 * B.ngv : B.ncx + 2 * B.ngc;
     const int isy = TO_CC ? B.ncy + 1 + 2 * B.ngv : B.ncy + 2 * B.ngc;
     const int isz = TO_CC ? B.ncz + 1 + 2 * B.ngv : B.ncz + 2 * B.ngc;
@@ -101,49 +111,73 @@ interp_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, const doubl
     const long long ifs = TO_CC ? B.vc_stride : B.cc_stride;
     const long long obase = TO_CC ? B.cg_offset : B.vm_offset;
     const long long ofs = TO_CC ? B.cc_stride : B.vc_stride;
-    // stored output index of tile-local output 0
-    const int out0[3] = {TO_CC ? o[0] : o[0] + B.ngv, TO_CC ? o[1] : o[1] + B.ngv,
-                         TO_CC ? o[2] : o[2] + B.ngv};
+    const int og = TO_CC ? 0 : B.ngv;   // stored output index = tile origin + local + og
+    const int t = threadIdx.x, tx = t % ITX, ty = t / ITX;
+    const bool col_ok = tx >= lo[0] && tx < hi[0] && ty >= lo[1] && ty < hi[1];
+    // plane element q of this thread: input offset within a plane (positions
+    // outside the stored array are clamped into it; they feed only outputs
+    // outside the call's range)
+    long long eoff[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        const int e = t + q * INT_;
+        const int lx = e % LX, ly = e / LX;
+        const int gx = min(max(in0[0] + lx, 0), isx - 1);
+        const int gy = min(max(in0[1] + ly, 0), isy - 1);
+        eoff[q] = gx + (long long)isx * gy;
+    }
+    const long long pstride = (long long)isx * isy;
     constexpr int NF = TO_CC ? 7 : 10;
-    const int t = threadIdx.x;
     for (int f = 0; f < NF; ++f) {
         const double *src = in + ibase + f * ifs;
-        // input box; positions outside the stored array are clamped into it
-        // (they feed only outputs outside the call's range)
-        for (int e = t; e < LX * LY * LZ; e += MNT) {
-            const int lx = e % LX, r = e / LX, ly = r % LY, lz = r / LY;
-            const int gx = min(max(in0[0] + lx, 0), isx - 1);
-            const int gy = min(max(in0[1] + ly, 0), isy - 1);
-            const int gz = min(max(in0[2] + lz, 0), isz - 1);
-            s_in[e] = src[gx + (long long)isx * (gy + (long long)isy * gz)];
-        }
-        __syncthreads();
-        for (int e = t; e < MTX * LY * LZ; e += MNT) {
-            const int x = e % MTX, r = e / MTX;   // r = ly + LY * lz
-            s_x[e] = midsum<O>(s_in + r * LX + x, 1);
-        }
-        __syncthreads();
-        for (int e = t; e < MTX * MTY * LZ; e += MNT) {
-            const int x = e % MTX, r = e / MTX, y = r % MTY, z = r / MTY;
-            s_y[e] = midsum<O>(s_x + (z * LY + y) * MTX + x, MTX);
-        }
-        __syncthreads();
         double *dst = out + obase + f * ofs;
-        for (int e = t; e < MOUT; e += MNT) {
-            const int x = e % MTX, r = e / MTX, y = r % MTY, z = r / MTY;
-            if (x >= lo[0] && x < hi[0] && y >= lo[1] && y < hi[1] && z >= lo[2] && z < hi[2]) {
-                const double v = midsum<O>(s_y + (z * MTY + y) * MTX + x, MTX * MTY);
-                dst[(out0[0] + x) + (long long)osx * ((out0[1] + y) + (long long)osy * (out0[2] + z))] = v;
+        double r[NLD];
+        auto load = [&](int p) __attribute__((always_inline)) {
+            const long long zo = min(max(in0[2] + p, 0), isz - 1) * pstride;
+#pragma unroll
+            for (int q = 0; q < NLD; ++q)
+                if ((q + 1) * INT_ <= NPL || t + q * INT_ < NPL)
+                    r[q] = src[zo + eoff[q]];
+        };
+        load(0);
+        double col[O];   // y-reduced values of the last O input planes
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int q = 0; q < NLD; ++q)
+                if ((q + 1) * INT_ <= NPL || t + q * INT_ < NPL)
+                    s_pl[t + q * INT_] = r[q];
+            if (p + 1 < NP)
+                load(p + 1);
+            __syncthreads();
+            for (int e = t; e < ITX * LY; e += INT_) {
+                const int x = e % ITX, ly = e / ITX;
+                s_x[e] = midsum<O>(s_pl + ly * LX + x, 1);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k + 1 < O; ++k)
+                col[k] = col[k + 1];
+            col[O - 1] = midsum<O>(s_x + ty * ITX + tx, ITX);
+            if (p >= O - 1) {
+                const int z = p - (O - 1);
+                if (col_ok && z >= lo[2] && z < hi[2]) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < O; ++k)
+                        v += midw<O>(k) * col[k];
+                    dst[(o[0] + og + tx) + (long long)osx * ((o[1] + og + ty)
+                        + (long long)osy * (o[2] + og + z))] = v;
+                }
             }
         }
-        __syncthreads();   // the LDS boxes are refilled for the next field
     }
 }
 
 // ADM projections at the cells of one tile (stored CC index in
 // [ngc - ext, ngc + nc + ext)).
 template <bool MHD>
-__global__ void __launch_bounds__(MNT)
+__global__ void __launch_bounds__(PNT)
 adm_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, double gfac, double chi_floor,
            const double *geom, const double *prim, double *adm)
 {
@@ -153,10 +187,11 @@ adm_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, double gfac, d
     const long long fs = B.cc_stride;
     const int a0 = B.ngc - ext;
     const int ax = B.ngc + B.ncx + ext, ay = B.ngc + B.ncy + ext, az = B.ngc + B.ncz + ext;
-    for (int e = threadIdx.x; e < MOUT; e += MNT) {
-        const int x = T.i0 + e % MTX, r = e / MTX, y = T.j0 + r % MTY, z = T.k0 + r / MTY;
+    {
+        const int e = threadIdx.x;
+        const int x = T.i0 + e % PTX, r = e / PTX, y = T.j0 + r % PTY, z = T.k0 + r / PTY;
         if (x < a0 || y < a0 || z < a0 || x >= ax || y >= ay || z >= az)
-            continue;
+            return;
         const long long p = x + (long long)sx * (y + (long long)sy * z);
         const double *g = geom + B.cg_offset + p;
         const double *w = prim + B.cp_offset + p;
@@ -214,11 +249,11 @@ hipError_t launch_interp(int order, const z4c_mplan *P, int ext, const double *i
     if (n == 0)
         return hipSuccess;
     if (order == 2)
-        interp_kernel<2, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+        interp_kernel<2, TO_CC><<<n, INT_, 0, s>>>(P->blocks_d, tiles, ext, in, out);
     else if (order == 4)
-        interp_kernel<4, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+        interp_kernel<4, TO_CC><<<n, INT_, 0, s>>>(P->blocks_d, tiles, ext, in, out);
     else
-        interp_kernel<6, TO_CC><<<n, MNT, 0, s>>>(P->blocks_d, tiles, ext, in, out);
+        interp_kernel<6, TO_CC><<<n, INT_, 0, s>>>(P->blocks_d, tiles, ext, in, out);
     return hipGetLastError();
 }
 
@@ -256,7 +291,7 @@ z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4
         return set_error(Z4C_EINVAL, "blocks is NULL or nblocks < 1");
     if (flags & ~Z4C_PLAN_NO_DEVICE)
         return set_error(Z4C_EINVAL, "unknown flags");
-    std::vector<MTile> cc, vc;
+    std::vector<MTile> cc, vc, pt;
     for (int b = 0; b < nblocks; ++b) {
         const z4c_mblock &B = blocks[b];
         char buf[160];
@@ -278,27 +313,35 @@ z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4
             return set_error(Z4C_EINVAL, buf);
         }
         const int sc[3] = {B.ncx + 2 * B.ngc, B.ncy + 2 * B.ngc, B.ncz + 2 * B.ngc};
-        for (int k = 0; k < sc[2]; k += MTZ)
-            for (int j = 0; j < sc[1]; j += MTY)
-                for (int i = 0; i < sc[0]; i += MTX)
+        for (int k = 0; k < sc[2]; k += ITZ)
+            for (int j = 0; j < sc[1]; j += ITY)
+                for (int i = 0; i < sc[0]; i += ITX)
                     cc.push_back({b, i, j, k});
-        for (int k = 0; k <= B.ncz; k += MTZ)
-            for (int j = 0; j <= B.ncy; j += MTY)
-                for (int i = 0; i <= B.ncx; i += MTX)
+        for (int k = 0; k <= B.ncz; k += ITZ)
+            for (int j = 0; j <= B.ncy; j += ITY)
+                for (int i = 0; i <= B.ncx; i += ITX)
                     vc.push_back({b, i, j, k});
+        for (int k = 0; k < sc[2]; k += PTZ)
+            for (int j = 0; j < sc[1]; j += PTY)
+                for (int i = 0; i < sc[0]; i += PTX)
+                    pt.push_back({b, i, j, k});
     }
-    if (cc.size() > (size_t)INT32_MAX || vc.size() > (size_t)INT32_MAX)
+    if (cc.size() > (size_t)INT32_MAX || vc.size() > (size_t)INT32_MAX
+        || pt.size() > (size_t)INT32_MAX)
         return set_error(Z4C_EINVAL, "too many tiles");
     z4c_mplan *P = new z4c_mplan;
     P->blocks.assign(blocks, blocks + nblocks);
     P->n_cc = (int)cc.size();
     P->n_vc = (int)vc.size();
+    P->n_pt = (int)pt.size();
     if (!(flags & Z4C_PLAN_NO_DEVICE)) {
         hipError_t e = hipMalloc(&P->blocks_d, sizeof(z4c_mblock) * nblocks);
         if (e == hipSuccess)
             e = hipMalloc(&P->cc_tiles_d, sizeof(MTile) * cc.size());
         if (e == hipSuccess)
             e = hipMalloc(&P->vc_tiles_d, sizeof(MTile) * vc.size());
+        if (e == hipSuccess)
+            e = hipMalloc(&P->pt_tiles_d, sizeof(MTile) * pt.size());
         if (e == hipSuccess)
             e = hipMemcpy(P->blocks_d, blocks, sizeof(z4c_mblock) * nblocks,
                           hipMemcpyHostToDevice);
@@ -307,6 +350,9 @@ z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4
                           hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(P->vc_tiles_d, vc.data(), sizeof(MTile) * vc.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(P->pt_tiles_d, pt.data(), sizeof(MTile) * pt.size(),
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             z4c_mplan_destroy(P);
@@ -329,6 +375,8 @@ z4c_status z4c_mplan_destroy(z4c_mplan *P)
         (void)hipFree(P->cc_tiles_d);
     if (P->vc_tiles_d)
         (void)hipFree(P->vc_tiles_d);
+    if (P->pt_tiles_d)
+        (void)hipFree(P->pt_tiles_d);
     delete P;
     return Z4C_OK;
 }
@@ -427,15 +475,15 @@ z4c_status z4c_adm_sources(const z4c_mplan *P, const z4c_fluid *fluid, int ext,
         }
     if ((st = check_plan(P)) != Z4C_OK)
         return st;
-    if (P->n_cc == 0)
+    if (P->n_pt == 0)
         return Z4C_OK;
     const double gfac = fluid->gamma_ad / (fluid->gamma_ad - 1.0);
-    const MTile *tiles = (const MTile *)P->cc_tiles_d;
+    const MTile *tiles = (const MTile *)P->pt_tiles_d;
     if (fluid->mhd)
-        adm_kernel<true><<<P->n_cc, MNT, 0, (hipStream_t)stream>>>(
+        adm_kernel<true><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(
             P->blocks_d, tiles, ext, gfac, fluid->chi_floor, geom, prim, adm);
     else
-        adm_kernel<false><<<P->n_cc, MNT, 0, (hipStream_t)stream>>>(
+        adm_kernel<false><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(
             P->blocks_d, tiles, ext, gfac, fluid->chi_floor, geom, prim, adm);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? Z4C_OK : set_hip_error(e, "ADM source kernel launch");
