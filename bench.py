@@ -175,6 +175,22 @@ def main():
         del regs
         plan.close()
 
+    # measured device-to-device copy of 1 GiB (what HBM sustains in practice)
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cms = []
+    for _ in range(10):
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cms.append(e0.elapsed_time(e1))
+    copy_gbs = 2.0 * a.numel() * 8 / (float(np.median(cms)) * 1e-3) / 1e9
+    del a, b
+
     r64 = results["fp64"]
     value = n_int * nstages / (r64["ms"] * 1e-3)
     # roofline of the dominant launch, a fused RHS + RK4 stage-2 launch:
@@ -222,6 +238,7 @@ def main():
                       f"{STAGE_BYTES[1]} algorithmic B per interior point",
         },
         "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
+        "hbm_copy_gbs": copy_gbs,
         "fp64_flop_per_pt_stage": FLOP_PER_PT_STAGE,
         "fp64_alu_frac": value * FLOP_PER_PT_STAGE / (FP64_PEAK_TFLOPS * 1e12),
     }

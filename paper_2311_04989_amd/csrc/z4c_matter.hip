@@ -4,14 +4,15 @@
 // the perfect-fluid / ideal-GRMHD stress-energy tensor (Sec. 2.1, 2.2).
 //
 // Interpolation is separable and marches along z: a workgroup of 256
-// threads owns a 16 x 16 column of outputs and ITZ output planes; for each
-// input plane it stages the (16 + order - 1)^2 inputs in LDS (the next plane
-// already in flight in registers), reduces them along x and then y, and each
+// threads owns an ITX x ITY column of outputs and ITZ output planes; for each
+// input plane it stages the (ITX + order - 1)(ITY + order - 1) inputs in LDS
+// (the next planes already in flight in registers), reduces them along x and
+// then y, and each
 // thread keeps the y-reduced values of the last `order` planes in registers
 // for the z reduction, so every input plane is read once per column and the
 // z halo costs (order - 1) / ITZ extra planes.  The ADM projections are
-// pointwise, one cell per thread.  Both kernels are HBM-bound; every row of
-// 16 doubles is one 128-byte request.
+// pointwise, one cell per thread over contiguous chunks of stored cells.
+// Both kernels are HBM-bound.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -34,9 +35,13 @@ namespace z4c {
 namespace {
 
 // interpolation columns: ITX x ITY outputs per plane, ITZ planes, one thread per (x, y)
-constexpr int ITX = 16, ITY = 16, ITZ = 16, INT_ = ITX * ITY;
-// point tiles of the ADM projections: one cell per thread
-constexpr int PTX = 16, PTY = 8, PTZ = 4, PNT = PTX * PTY * PTZ;
+// (32 x 8 x 16 and four planes in flight measured best on the 8 x 128^3-cell
+// level set among 16 x 16, 32 x 16 and 32 x 8 columns of 16 or 32 planes and
+// one to six planes in flight)
+constexpr int ITX = 32, ITY = 8, ITZ = 16, INT_ = ITX * ITY;
+constexpr int PD = 4;   // input planes in flight per workgroup
+// ADM projections: chunks of PNT consecutive stored cells, one per thread
+constexpr int PNT = 512;
 
 struct MTile {
     int block, i0, j0, k0;   // tile origin (stored CC index, or vertex index)
@@ -131,24 +136,26 @@ interp_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, const doubl
     for (int f = 0; f < NF; ++f) {
         const double *src = in + ibase + f * ifs;
         double *dst = out + obase + f * ofs;
-        double r[NLD];
+        double r[PD][NLD];   // planes p .. p + PD - 1 in flight
         auto load = [&](int p) __attribute__((always_inline)) {
             const long long zo = min(max(in0[2] + p, 0), isz - 1) * pstride;
 #pragma unroll
             for (int q = 0; q < NLD; ++q)
                 if ((q + 1) * INT_ <= NPL || t + q * INT_ < NPL)
-                    r[q] = src[zo + eoff[q]];
+                    r[p % PD][q] = src[zo + eoff[q]];
         };
-        load(0);
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            load(p);
         double col[O];   // y-reduced values of the last O input planes
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
             for (int q = 0; q < NLD; ++q)
                 if ((q + 1) * INT_ <= NPL || t + q * INT_ < NPL)
-                    s_pl[t + q * INT_] = r[q];
-            if (p + 1 < NP)
-                load(p + 1);
+                    s_pl[t + q * INT_] = r[p % PD][q];
+            if (p + PD < NP)
+                load(p + PD);
             __syncthreads();
             for (int e = t; e < ITX * LY; e += INT_) {
                 const int x = e % ITX, ly = e / ITX;
@@ -188,11 +195,14 @@ adm_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, double gfac, d
     const int a0 = B.ngc - ext;
     const int ax = B.ngc + B.ncx + ext, ay = B.ngc + B.ncy + ext, az = B.ngc + B.ncz + ext;
     {
-        const int e = threadIdx.x;
-        const int x = T.i0 + e % PTX, r = e / PTX, y = T.j0 + r % PTY, z = T.k0 + r / PTY;
+        // T.i0: first stored cell (linear index) of the chunk
+        const long long lin = (long long)T.i0 + threadIdx.x;
+        if (lin >= (long long)sx * sy * (B.ncz + 2 * B.ngc))
+            return;
+        const int x = (int)(lin % sx), r = (int)(lin / sx), y = r % sy, z = r / sy;
         if (x < a0 || y < a0 || z < a0 || x >= ax || y >= ay || z >= az)
             return;
-        const long long p = x + (long long)sx * (y + (long long)sy * z);
+        const long long p = lin;
         const double *g = geom + B.cg_offset + p;
         const double *w = prim + B.cp_offset + p;
         const double chi = g[0];
@@ -321,10 +331,13 @@ z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4
             for (int j = 0; j <= B.ncy; j += ITY)
                 for (int i = 0; i <= B.ncx; i += ITX)
                     vc.push_back({b, i, j, k});
-        for (int k = 0; k < sc[2]; k += PTZ)
-            for (int j = 0; j < sc[1]; j += PTY)
-                for (int i = 0; i < sc[0]; i += PTX)
-                    pt.push_back({b, i, j, k});
+        const long long ncs = (long long)sc[0] * sc[1] * sc[2];
+        if (ncs > INT32_MAX) {
+            snprintf(buf, sizeof buf, "block %d: more than 2^31 stored cells", b);
+            return set_error(Z4C_EINVAL, buf);
+        }
+        for (long long c = 0; c < ncs; c += PNT)
+            pt.push_back({b, (int)c, 0, 0});
     }
     if (cc.size() > (size_t)INT32_MAX || vc.size() > (size_t)INT32_MAX
         || pt.size() > (size_t)INT32_MAX)
