@@ -30,6 +30,9 @@
  *              the Eulerian magnetic field (the sqrt(4 pi) absorbed, Sec. 2.2);
  *              the B fields are not read for pure hydrodynamics
  *   CC adm     10 fields, the layout of VC matter
+ *   CC cons    8 fields D, S_x, S_y, S_z, tau, B^x, B^y, B^z: the conservative
+ *              variables of Sec. 2.2, densitised by sqrt(gamma) (B^k too)
+ *   CC status  one int per stored cell (primitive recovery)
  *
  * Interpolation: along each direction the Lagrange polynomial through the
  * `order` nearest input points (order 2, 4 or 6) evaluated midway between the
@@ -50,7 +53,7 @@
 extern "C" {
 #endif
 
-/* One MeshBlock of the matter coupling (80 bytes). */
+/* One MeshBlock of the matter coupling (96 bytes). */
 typedef struct {
     long long vs_offset;   /* VC state array: element offset of field 0, vertex (-ngv,-ngv,-ngv) */
     long long vm_offset;   /* VC matter array: the same                                      */
@@ -58,6 +61,8 @@ typedef struct {
     long long cg_offset;   /* CC geometry array: element offset of field 0, cell (-ngc,...)   */
     long long cp_offset;   /* CC primitive array                                              */
     long long ca_offset;   /* CC ADM-source array                                             */
+    long long cq_offset;   /* CC conservative array                                           */
+    long long cf_offset;   /* CC status array (one int per stored cell, no fields)            */
     long long cc_stride;   /* elements between consecutive fields of any CC array             */
     int ncx, ncy, ncz;     /* cells per direction, >= 1                                       */
     int ngv, ngc;          /* ghost layers stored in the VC / CC arrays, >= 0                 */
@@ -114,6 +119,47 @@ z4c_status z4c_adm_sources(const z4c_mplan *plan, const z4c_fluid *fluid, int ex
  * block (else Z4C_ENOGHOST).  Ghost vertices of `matter` are not written. */
 z4c_status z4c_sources_to_vc(const z4c_mplan *plan, int order, const double *adm, double *matter,
                              void *hip_stream);
+
+/* Primitive recovery (Sec. 3.2, conservative-to-primitive inversion, and
+ * Appendix A).  Ideal gas p = (Gamma - 1) rho eps.  Per cell, with
+ * gamma_ij = gt_ij / max(chi, chi_floor) from the CC geometry:
+ *   - the conservatives are undensitised; if D / sqrt(gamma) < f_thr rho_atm
+ *     the cell becomes atmosphere (status 1);
+ *   - otherwise the inversion is the root in mu = 1 / (h W) of the master
+ *     function of Kastaun, Kalinani & Ciolfi (the algorithm the paper's
+ *     primitive solver is based on): bracketed in [0, mu+] (mu+ from their
+ *     auxiliary function), Illinois iterations to a relative width `tol` or
+ *     `max_iter` iterations; no sign change or no convergence: atmosphere
+ *     (status 3);
+ *   - a solution with |ut| = sqrt(W^2 - 1) above ut_max (the velocity
+ *     ceiling), or with rho < f_thr rho_atm, becomes atmosphere (status 2 /
+ *     status 1);
+ *   - atmosphere: rho = rho_atm, ut^i = 0, p = p_atm, B unchanged, and the
+ *     conservatives of that state written back (Sec. 3.2: atmosphere
+ *     treatment).  Status 0: recovered.
+ * `prim` receives rho, ut^i, p and (mhd) the undensitised B^i. */
+typedef struct {
+    int mhd;               /* 0: no magnetic field (B fields neither read nor written) */
+    double gamma_ad;       /* > 1                                                      */
+    double chi_floor;      /* > 0                                                      */
+    double rho_atm, p_atm; /* atmosphere density (> 0) and pressure (>= 0)             */
+    double f_thr;          /* atmosphere threshold factor (>= 0; the paper uses 1)     */
+    double ut_max;         /* velocity ceiling on |ut| (> 0; the paper uses 20)        */
+    double tol;            /* relative width of the final bracket of mu (> 0)          */
+    int max_iter;          /* >= 1                                                     */
+} z4c_c2p_params;
+
+/* Conservatives of the primitives (Sec. 2.2) at cells [-ext, nc + ext):
+ * from `geom` and `prim` (rho, ut^i, p, B^i) to `cons` (densitised).
+ * Uses mhd, gamma_ad, chi_floor of `c`. */
+z4c_status z4c_p2c(const z4c_mplan *plan, const z4c_c2p_params *c, int ext, const double *geom,
+                   const double *prim, double *cons, void *hip_stream);
+
+/* Primitive recovery at cells [-ext, nc + ext): `cons` (read; rewritten at
+ * atmosphere cells) to `prim`; `status` (may be NULL) receives the status
+ * of every cell in the range. */
+z4c_status z4c_c2p(const z4c_mplan *plan, const z4c_c2p_params *c, int ext, const double *geom,
+                   double *cons, double *prim, int *status, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -250,6 +250,317 @@ adm_kernel(const z4c_mblock *blocks, const MTile *tiles, int ext, double gfac, d
     }
 }
 
+// ---- primitive <-> conservative maps (ideal gas, Sec. 2.2; Appendix A) ----
+
+struct C2PArgs {
+    const z4c_mblock *blocks;
+    const MTile *tiles;
+    int ext, mhd, max_iter;
+    double gm1, chi_floor, rho_atm, p_atm, eps_atm, rho_thr, vmax2, ut_max2, tol;
+    const double *geom;
+    const double *prim_in;    // p2c
+    double *cons;
+    double *prim;             // c2p
+    int *status;
+};
+
+// Cell of one thread (chunk of consecutive stored cells) or -1 when it lies
+// outside [ngc - ext, ngc + nc + ext) per direction.
+__device__ __forceinline__ long long chunk_cell(const z4c_mblock &B, const MTile &T, int ext)
+{
+    const int sx = B.ncx + 2 * B.ngc, sy = B.ncy + 2 * B.ngc;
+    const long long lin = (long long)T.i0 + threadIdx.x;
+    if (lin >= (long long)sx * sy * (B.ncz + 2 * B.ngc))
+        return -1;
+    const int x = (int)(lin % sx), r = (int)(lin / sx), y = r % sy, z = r / sy;
+    const int a0 = B.ngc - ext;
+    if (x < a0 || y < a0 || z < a0 || x >= B.ngc + B.ncx + ext || y >= B.ngc + B.ncy + ext
+        || z >= B.ngc + B.ncz + ext)
+        return -1;
+    return lin;
+}
+
+// gamma_ij (6, symmetric storage) from the CC geometry, its determinant.
+__device__ __forceinline__ double cell_metric(const double *g, long long fs, double chi_floor,
+                                              double gam[6])
+{
+    const double chi = g[0];
+    const double ic = 1.0 / (chi > chi_floor ? chi : chi_floor);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        gam[q] = g[(1 + q) * fs] * ic;
+    return gam[0] * (gam[3] * gam[5] - gam[4] * gam[4]) - gam[1] * (gam[1] * gam[5] - gam[4] * gam[2])
+         + gam[2] * (gam[1] * gam[4] - gam[3] * gam[2]);
+}
+
+__device__ __forceinline__ void lower(const double gam[6], const double u[3], double l[3])
+{
+    l[0] = gam[0] * u[0] + gam[1] * u[1] + gam[2] * u[2];
+    l[1] = gam[1] * u[0] + gam[3] * u[1] + gam[4] * u[2];
+    l[2] = gam[2] * u[0] + gam[4] * u[1] + gam[5] * u[2];
+}
+
+// Conservatives (densitised) of rho, ut^i, p, B^i.  With W^2 = 1 + ut.ut,
+// v_i = ut_i / W, alpha b^0 = W B.v, b_i = B_i / W + alpha b^0 v_i,
+// b^2 = ((alpha b^0)^2 + B^2) / W^2 (the lapse cancels):
+//   D = sg rho W,  S_j = sg ((rho h + b^2) W ut_j - alpha b^0 b_j),
+//   tau = sg ((rho h + b^2) W^2 - rho W - (p + b^2/2) - (alpha b^0)^2).
+template <bool MHD>
+__device__ __forceinline__ void p2c_point(const double gam[6], double sg, double gm1, double rho,
+                                          const double ut[3], double p, const double Bu[3],
+                                          double q[8])
+{
+    double ul[3];
+    lower(gam, ut, ul);
+    const double W2 = 1.0 + ul[0] * ut[0] + ul[1] * ut[1] + ul[2] * ut[2];
+    const double W = sqrt(W2);
+    const double rhoh = rho + (1.0 + 1.0 / gm1) * p;   // rho (1 + eps) + p
+    double ab0 = 0.0, b2 = 0.0, bl[3] = {0.0, 0.0, 0.0};
+    if constexpr (MHD) {
+        double Bl[3];
+        lower(gam, Bu, Bl);
+        const double iW = 1.0 / W;
+        ab0 = (Bu[0] * ul[0] + Bu[1] * ul[1] + Bu[2] * ul[2]);         // W B.v = B.ut
+        b2 = (ab0 * ab0 + Bl[0] * Bu[0] + Bl[1] * Bu[1] + Bl[2] * Bu[2]) * iW * iW;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            bl[i] = Bl[i] * iW + ab0 * ul[i] * iW;                        // v_i = ut_i / W
+    }
+    const double e = rhoh + b2;
+    q[0] = sg * rho * W;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        q[1 + i] = sg * (e * W * ul[i] - ab0 * bl[i]);
+    q[4] = sg * (e * W2 - rho * W - (p + 0.5 * b2) - ab0 * ab0);
+    if constexpr (MHD) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            q[5 + i] = sg * Bu[i];
+    }
+}
+
+template <bool MHD>
+__global__ void __launch_bounds__(PNT) p2c_kernel(const C2PArgs a)
+{
+    const MTile T = a.tiles[blockIdx.x];
+    const z4c_mblock B = a.blocks[T.block];
+    const long long p = chunk_cell(B, T, a.ext);
+    if (p < 0)
+        return;
+    const long long fs = B.cc_stride;
+    double gam[6];
+    const double sg = sqrt(cell_metric(a.geom + B.cg_offset + p, fs, a.chi_floor, gam));
+    const double *w = a.prim_in + B.cp_offset + p;
+    const double ut[3] = {w[fs], w[2 * fs], w[3 * fs]};
+    double Bu[3] = {0.0, 0.0, 0.0};
+    if constexpr (MHD) {
+        Bu[0] = w[5 * fs];
+        Bu[1] = w[6 * fs];
+        Bu[2] = w[7 * fs];
+    }
+    double q[8];
+    p2c_point<MHD>(gam, sg, a.gm1, w[0], ut, w[4 * fs], Bu, q);
+    double *o = a.cons + B.cq_offset + p;
+    constexpr int NQ = MHD ? 8 : 5;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        o[i * fs] = q[i];
+}
+
+// Primitive recovery of one cell: the master function f(mu) = mu - mu_hat(mu)
+// of Kastaun, Kalinani & Ciolfi in mu = 1 / (h W), with the normalised
+// conservatives q = tau / D, r_i = S_i / D, b^i = B^i / sqrt(D) (all
+// undensitised):
+//   x = 1 / (1 + mu b^2),  rbar^2 = x^2 r^2 + mu x (1 + x) (r.b)^2,
+//   qbar = q - b^2/2 - mu^2 x^2 (b^2 r^2 - (r.b)^2) / 2,
+//   v^2 = min(mu^2 rbar^2, vmax^2),  W = 1 / sqrt(1 - v^2),  rho = D / W,
+//   eps = max(W (qbar - mu rbar^2) + v^2 W^2 / (1 + W), 0),
+//   a = p / (rho (1 + eps)),  h = (1 + eps)(1 + a),
+//   nu = max(h / W, (1 + a)(1 + qbar - mu rbar^2)),  mu_hat = 1 / (nu + mu rbar^2).
+struct Master {
+    double D, q, r2, b2, rb2, gm1, vmax2;
+    __device__ __forceinline__ double x(double mu) const { return 1.0 / (1.0 + mu * b2); }
+    __device__ __forceinline__ double rbar2(double mu) const
+    {
+        const double xx = x(mu);
+        return r2 * xx * xx + mu * xx * (1.0 + xx) * rb2;
+    }
+    __device__ __forceinline__ double f(double mu, double &W, double &eps) const
+    {
+        const double xx = x(mu);
+        const double rb = r2 * xx * xx + mu * xx * (1.0 + xx) * rb2;
+        const double qb = q - 0.5 * b2 - 0.5 * mu * mu * xx * xx * (b2 * r2 - rb2);
+        const double v2 = fmin(mu * mu * rb, vmax2);
+        W = 1.0 / sqrt(1.0 - v2);
+        const double rho = D / W;
+        const double e = W * (qb - mu * rb) + v2 * W * W / (1.0 + W);
+        eps = e > 0.0 ? e : 0.0;
+        const double pr = gm1 * rho * eps;
+        const double aa = pr / (rho * (1.0 + eps));
+        const double h = (1.0 + eps) * (1.0 + aa);
+        const double nu = fmax(h / W, (1.0 + aa) * (1.0 + qb - mu * rb));
+        return mu - 1.0 / (nu + mu * rb);
+    }
+};
+
+// Illinois iterations for a sign change of fn on [lo, hi] (fn(lo) < 0 <=
+// fn(hi)), every fourth step a bisection (the bracket shrinks whatever fn
+// does); converged when the bracket is narrower than tol * hi or one ulp;
+// returns false after max_iter steps without convergence.
+template <typename Fn>
+__device__ __forceinline__ bool illinois(Fn fn, double lo, double hi, double flo, double fhi,
+                                         double tol, int max_iter, double &root)
+{
+    int side = 0;
+    for (int it = 0; it < max_iter; ++it) {
+        double m = (lo * fhi - hi * flo) / (fhi - flo);
+        if (!(m > lo && m < hi) || (it & 3) == 3)
+            m = 0.5 * (lo + hi);
+        if (!(m > lo && m < hi)) {
+            root = m;
+            return true;
+        }
+        const double fm = fn(m);
+        if (fm == 0.0) {
+            root = m;
+            return true;
+        }
+        if (fm < 0.0) {
+            lo = m;
+            flo = fm;
+            if (side == -1)
+                fhi *= 0.5;
+            side = -1;
+        } else {
+            hi = m;
+            fhi = fm;
+            if (side == 1)
+                flo *= 0.5;
+            side = 1;
+        }
+        if (hi - lo <= tol * hi) {
+            root = 0.5 * (lo + hi);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <bool MHD>
+__global__ void __launch_bounds__(PNT) c2p_kernel(const C2PArgs a)
+{
+    const MTile T = a.tiles[blockIdx.x];
+    const z4c_mblock B = a.blocks[T.block];
+    const long long p = chunk_cell(B, T, a.ext);
+    if (p < 0)
+        return;
+    const long long fs = B.cc_stride;
+    double gam[6];
+    const double det = cell_metric(a.geom + B.cg_offset + p, fs, a.chi_floor, gam);
+    const double sg = sqrt(det), isg = 1.0 / sg;
+    double *c = a.cons + B.cq_offset + p;
+    const double D = c[0] * isg;
+    const double Sl[3] = {c[fs] * isg, c[2 * fs] * isg, c[3 * fs] * isg};
+    const double tau = c[4 * fs] * isg;
+    double Bu[3] = {0.0, 0.0, 0.0};
+    if constexpr (MHD) {
+        Bu[0] = c[5 * fs] * isg;
+        Bu[1] = c[6 * fs] * isg;
+        Bu[2] = c[7 * fs] * isg;
+    }
+    int st = 0;
+    double rho = 0.0, pr = 0.0, ut[3] = {0.0, 0.0, 0.0};
+    if (!(D >= a.rho_thr)) {
+        st = 1;
+    } else {
+        // inverse metric
+        const double id = 1.0 / det;
+        const double gi[6] = {(gam[3] * gam[5] - gam[4] * gam[4]) * id,
+                              (gam[2] * gam[4] - gam[1] * gam[5]) * id,
+                              (gam[1] * gam[4] - gam[2] * gam[3]) * id,
+                              (gam[0] * gam[5] - gam[2] * gam[2]) * id,
+                              (gam[2] * gam[1] - gam[0] * gam[4]) * id,
+                              (gam[0] * gam[3] - gam[1] * gam[1]) * id};
+        const double iD = 1.0 / D;
+        const double rl[3] = {Sl[0] * iD, Sl[1] * iD, Sl[2] * iD};
+        double ru[3];
+        lower(gi, rl, ru);                                    // r^i = gamma^ij r_j
+        const double sD = 1.0 / sqrt(D);
+        const double bu[3] = {Bu[0] * sD, Bu[1] * sD, Bu[2] * sD};
+        double bl[3];
+        lower(gam, bu, bl);
+        Master M;
+        M.D = D;
+        M.q = tau * iD;
+        M.r2 = rl[0] * ru[0] + rl[1] * ru[1] + rl[2] * ru[2];
+        M.b2 = bl[0] * bu[0] + bl[1] * bu[1] + bl[2] * bu[2];
+        const double rb = rl[0] * bu[0] + rl[1] * bu[1] + rl[2] * bu[2];
+        M.rb2 = rb * rb;
+        M.gm1 = a.gm1;
+        M.vmax2 = a.vmax2;
+        // bracket [0, mu+]: mu+ is the root of mu sqrt(1 + rbar^2(mu)) - 1
+        // (minimum enthalpy 1) when it lies below 1
+        double mup = 1.0;
+        const double fa1 = sqrt(1.0 + M.rbar2(1.0)) - 1.0;
+        bool ok = true;
+        if (fa1 > 0.0) {
+            auto fa = [&](double mu) { return mu * sqrt(1.0 + M.rbar2(mu)) - 1.0; };
+            ok = illinois(fa, 0.0, 1.0, -1.0, fa1, a.tol, a.max_iter, mup);
+        }
+        double W = 1.0, eps = 0.0, mu = 0.0;
+        if (ok) {
+            double Wd, ed;
+            auto fm = [&](double m) { return M.f(m, Wd, ed); };
+            const double f0 = fm(0.0), f1 = fm(mup);
+            if (f0 < 0.0 && f1 >= 0.0)
+                ok = illinois(fm, 0.0, mup, f0, f1, a.tol, a.max_iter, mu);
+            else if (f0 < 0.0 && f1 >= -1e-12 * mup)
+                mu = mup;   // cold gas (h = 1): the root is mu+ itself, f(mu+) = 0 up to rounding
+            else
+                ok = false;
+        }
+        if (!ok) {
+            st = 3;
+        } else {
+            M.f(mu, W, eps);
+            const double xx = M.x(mu);
+            const double s = mu * xx;
+            ut[0] = W * s * (ru[0] + mu * rb * bu[0]);
+            ut[1] = W * s * (ru[1] + mu * rb * bu[1]);
+            ut[2] = W * s * (ru[2] + mu * rb * bu[2]);
+            rho = D / W;
+            pr = a.gm1 * rho * eps;
+            if (mu * mu * M.rbar2(mu) >= a.vmax2 || W * W - 1.0 > a.ut_max2)
+                st = 2;
+            else if (!(rho >= a.rho_thr))
+                st = 1;
+        }
+    }
+    double *w = a.prim + B.cp_offset + p;
+    if (st != 0) {
+        rho = a.rho_atm;
+        pr = a.p_atm;
+        ut[0] = ut[1] = ut[2] = 0.0;
+        double q[8];
+        p2c_point<MHD>(gam, sg, a.gm1, rho, ut, pr, Bu, q);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            c[i * fs] = q[i];
+    }
+    w[0] = rho;
+    w[fs] = ut[0];
+    w[2 * fs] = ut[1];
+    w[3 * fs] = ut[2];
+    w[4 * fs] = pr;
+    if constexpr (MHD) {
+        w[5 * fs] = Bu[0];
+        w[6 * fs] = Bu[1];
+        w[7 * fs] = Bu[2];
+    }
+    if (a.status)
+        a.status[B.cf_offset + p] = st;
+}
+
 template <bool TO_CC>
 hipError_t launch_interp(int order, const z4c_mplan *P, int ext, const double *in, double *out,
                          hipStream_t s)
@@ -310,7 +621,8 @@ z4c_status z4c_mplan_create(const z4c_mblock *blocks, int nblocks, int flags, z4
             return set_error(Z4C_EINVAL, buf);
         }
         if (B.vs_offset < 0 || B.vm_offset < 0 || B.cg_offset < 0 || B.cp_offset < 0
-            || B.ca_offset < 0 || B.vc_stride < 0 || B.cc_stride < 0) {
+            || B.ca_offset < 0 || B.cq_offset < 0 || B.cf_offset < 0 || B.vc_stride < 0
+            || B.cc_stride < 0) {
             snprintf(buf, sizeof buf, "block %d: offsets and strides must be >= 0", b);
             return set_error(Z4C_EINVAL, buf);
         }
@@ -500,6 +812,100 @@ z4c_status z4c_adm_sources(const z4c_mplan *P, const z4c_fluid *fluid, int ext,
             P->blocks_d, tiles, ext, gfac, fluid->chi_floor, geom, prim, adm);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? Z4C_OK : set_hip_error(e, "ADM source kernel launch");
+}
+
+static z4c_status c2p_common(const z4c_mplan *P, const z4c_c2p_params *c, int ext,
+                             const void *geom, const void *a, const void *b, C2PArgs &A)
+{
+    if (!P)
+        return set_error(Z4C_EINVAL, "mplan is NULL");
+    if (!c || !geom || !a || !b)
+        return set_error(Z4C_EINVAL, "params and arrays must not be NULL");
+    if (c->mhd != 0 && c->mhd != 1)
+        return set_error(Z4C_EINVAL, "mhd must be 0 or 1");
+    if (!(c->gamma_ad > 1.0) || !std::isfinite(c->gamma_ad))
+        return set_error(Z4C_EINVAL, "gamma_ad must be finite and > 1");
+    if (!(c->chi_floor > 0.0) || !std::isfinite(c->chi_floor))
+        return set_error(Z4C_EINVAL, "chi_floor must be finite and > 0");
+    if (!(c->rho_atm > 0.0) || !(c->p_atm >= 0.0) || !(c->f_thr >= 0.0)
+        || !std::isfinite(c->rho_atm) || !std::isfinite(c->p_atm) || !std::isfinite(c->f_thr))
+        return set_error(Z4C_EINVAL, "rho_atm > 0, p_atm >= 0 and f_thr >= 0 must be finite");
+    if (!(c->ut_max > 0.0) || !std::isfinite(c->ut_max) || !(c->tol > 0.0) || c->max_iter < 1)
+        return set_error(Z4C_EINVAL, "ut_max and tol must be > 0, max_iter >= 1");
+    if (a == b || a == geom || b == geom)
+        return set_error(Z4C_EINVAL, "geom, input and output arrays must not alias");
+    if (!aligned8(geom) || !aligned8(a) || !aligned8(b))
+        return set_error(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (ext < 0)
+        return set_error(Z4C_EINVAL, "ext must be >= 0");
+    for (size_t k = 0; k < P->blocks.size(); ++k)
+        if (ext > P->blocks[k].ngc) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "block %zu: ext %d exceeds the %d stored ghost cells", k,
+                     ext, P->blocks[k].ngc);
+            return set_error(Z4C_EINVAL, buf);
+        }
+    z4c_status st = check_plan(P);
+    if (st != Z4C_OK)
+        return st;
+    A = C2PArgs{};
+    A.blocks = P->blocks_d;
+    A.tiles = (const MTile *)P->pt_tiles_d;
+    A.ext = ext;
+    A.mhd = c->mhd;
+    A.max_iter = c->max_iter;
+    A.gm1 = c->gamma_ad - 1.0;
+    A.chi_floor = c->chi_floor;
+    A.rho_atm = c->rho_atm;
+    A.p_atm = c->p_atm;
+    A.eps_atm = c->p_atm / ((c->gamma_ad - 1.0) * c->rho_atm);
+    A.rho_thr = c->f_thr * c->rho_atm;
+    A.ut_max2 = c->ut_max * c->ut_max;
+    A.vmax2 = A.ut_max2 / (1.0 + A.ut_max2);
+    A.tol = c->tol;
+    A.geom = (const double *)geom;
+    return Z4C_OK;
+}
+
+z4c_status z4c_p2c(const z4c_mplan *P, const z4c_c2p_params *c, int ext, const double *geom,
+                   const double *prim, double *cons, void *stream)
+{
+    C2PArgs A;
+    const z4c_status st = c2p_common(P, c, ext, geom, prim, cons, A);
+    if (st != Z4C_OK)
+        return st;
+    if (P->n_pt == 0)
+        return Z4C_OK;
+    A.prim_in = prim;
+    A.cons = cons;
+    if (c->mhd)
+        p2c_kernel<true><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(A);
+    else
+        p2c_kernel<false><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(A);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? Z4C_OK : set_hip_error(e, "p2c kernel launch");
+}
+
+z4c_status z4c_c2p(const z4c_mplan *P, const z4c_c2p_params *c, int ext, const double *geom,
+                   double *cons, double *prim, int *status, void *stream)
+{
+    C2PArgs A;
+    const z4c_status st = c2p_common(P, c, ext, geom, cons, prim, A);
+    if (st != Z4C_OK)
+        return st;
+    if (status && (((uintptr_t)status & 3u) != 0))
+        return set_error(Z4C_EALIGN, "status must be 4-byte aligned");
+    if (P->n_pt == 0)
+        return Z4C_OK;
+    A.cons = cons;
+    A.prim = prim;
+    A.status = status;
+    if (c->mhd)
+        c2p_kernel<true><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(A);
+    else
+        c2p_kernel<false><<<P->n_pt, PNT, 0, (hipStream_t)stream>>>(A);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? Z4C_OK : set_hip_error(e, "c2p kernel launch");
 }
 
 }  // extern "C"

@@ -482,6 +482,7 @@ PRIMS = ["rho", "utx", "uty", "utz", "p", "Bx", "By", "Bz"]
 MBLOCK_DTYPE = np.dtype([("vs_offset", np.int64), ("vm_offset", np.int64),
                          ("vc_stride", np.int64), ("cg_offset", np.int64),
                          ("cp_offset", np.int64), ("ca_offset", np.int64),
+                         ("cq_offset", np.int64), ("cf_offset", np.int64),
                          ("cc_stride", np.int64), ("ncx", np.int32), ("ncy", np.int32),
                          ("ncz", np.int32), ("ngv", np.int32), ("ngc", np.int32),
                          ("pad", np.int32)])
@@ -524,9 +525,10 @@ class MBlock:
 
 
 class MatterBatch:
-    """Blocks with their five arrays: VC state (22 fields), VC matter (10),
-    CC geometry (7), CC primitives (8), CC ADM sources (10); block-major,
-    fields strided by the per-block vertex / cell counts (padded to even)."""
+    """Blocks with their arrays: VC state (22 fields), VC matter (10), CC
+    geometry (7), CC primitives (8), CC ADM sources (10), CC conservatives
+    (8), CC status (one int32 per cell); block-major, fields strided by the
+    per-block vertex / cell counts (padded to even)."""
 
     def __init__(self, blocks: List[MBlock]):
         self.blocks = list(blocks)
@@ -538,7 +540,11 @@ class MatterBatch:
         self.vs_offset, self.vm_offset = NF * vstart[:-1], NM * vstart[:-1]
         self.cg_offset, self.cp_offset = NGEOM * cstart[:-1], NPRIM * cstart[:-1]
         self.ca_offset = NM * cstart[:-1]
+        self.cq_offset = NPRIM * cstart[:-1]
+        self.cf_offset = cstart[:-1].copy()
         nv, nc = int(vstart[-1]), int(cstart[-1])
+        self.cons = np.zeros(NPRIM * nc)
+        self.status = np.zeros(nc, dtype=np.int32)
         self.u = np.zeros(NF * nv)
         self.matter = np.zeros(NM * nv)
         self.geom = np.zeros(NGEOM * nc)
@@ -548,7 +554,8 @@ class MatterBatch:
 
     _KIND = {"u": ("vs_offset", "vc_stride", "vshape"), "matter": ("vm_offset", "vc_stride", "vshape"),
              "geom": ("cg_offset", "cc_stride", "cshape"), "prim": ("cp_offset", "cc_stride", "cshape"),
-             "adm": ("ca_offset", "cc_stride", "cshape")}
+             "adm": ("ca_offset", "cc_stride", "cshape"), "cons": ("cq_offset", "cc_stride", "cshape"),
+             "status": ("cf_offset", "cc_stride", "cshape")}
 
     def view(self, kind: str, arr: np.ndarray, b: int, f: int) -> np.ndarray:
         """Stored (ghosts included) field f of block b of an array of `kind`
@@ -563,8 +570,8 @@ class MatterBatch:
         t = np.zeros(len(self.blocks), dtype=MBLOCK_DTYPE)
         for i, b in enumerate(self.blocks):
             t[i] = (self.vs_offset[i], self.vm_offset[i], self.vc_stride[i], self.cg_offset[i],
-                    self.cp_offset[i], self.ca_offset[i], self.cc_stride[i], b.ncx, b.ncy, b.ncz,
-                    b.ngv, b.ngc, 0)
+                    self.cp_offset[i], self.ca_offset[i], self.cq_offset[i], self.cf_offset[i],
+                    self.cc_stride[i], b.ncx, b.ncy, b.ncz, b.ngv, b.ngc, 0)
         return t
 
     @property
@@ -642,3 +649,44 @@ def random_matter_batch(seed: int, nblocks: int = 3, nmax: int = 24, ngv: int = 
     fill_fluid(mb, rng, B0=3e-3, omega=0.04)
     mb.name = f"random matter blocks seed {seed}"
     return mb
+
+
+def c2p_states(mb: MatterBatch, rng, wmax=10.0, mag=10.0, n_atm=0, n_fast=0, ut_fast=30.0):
+    """Overwrite the CC geometry and primitives of every stored cell with
+    seeded independent states: a random symmetric positive conformal metric
+    (eigenvalues > 0.3) and chi in [0.3, 1]; rho log-uniform in [1e-8, 1e-2],
+    p / rho log-uniform in [1e-3, 10], W log-uniform in [1, wmax] along a
+    random direction, B with b^2 / rho log-uniform in [1e-4, mag].  Then
+    `n_atm` random cells per block get rho = 1e-16 (below any atmosphere
+    threshold used in the tests) and `n_fast` cells |ut| = ut_fast."""
+    for b, blk in enumerate(mb.blocks):
+        shape = blk.cshape
+        n = int(np.prod(shape))
+        a = rng.normal(size=(n, 3, 3))
+        g = np.eye(3)[None] + 0.15 * (a + np.transpose(a, (0, 2, 1)))
+        bad = np.linalg.eigvalsh(g).min(axis=1) <= 0.3
+        g[bad] = np.eye(3)
+        chi = rng.uniform(0.3, 1.0, size=n)
+        for q, (i, j) in enumerate(SYM):
+            mb.view("geom", mb.geom, b, 1 + q)[...] = g[:, i, j].reshape(shape)
+        mb.view("geom", mb.geom, b, 0)[...] = chi.reshape(shape)
+        gam = g / chi[:, None, None]
+        rho = 10.0 ** rng.uniform(-8.0, -2.0, size=n)
+        p = rho * 10.0 ** rng.uniform(-3.0, 1.0, size=n)
+        d = rng.normal(size=(n, 3))
+        d /= np.sqrt(np.einsum("ni,nij,nj->n", d, gam, d))[:, None]
+        W = 10.0 ** rng.uniform(0.0, math.log10(wmax), size=n)
+        ut = d * np.sqrt(W * W - 1.0)[:, None]
+        Bv = rng.normal(size=(n, 3))
+        Bv *= np.sqrt(rho * 10.0 ** rng.uniform(-4.0, math.log10(mag), size=n)
+                      / np.einsum("ni,nij,nj->n", Bv, gam, Bv))[:, None]
+        if n_atm:
+            idx = rng.choice(n, size=n_atm, replace=False)
+            rho[idx] = 1e-16
+            p[idx] = 1e-20
+        if n_fast:
+            idx = rng.choice(n, size=n_fast, replace=False)
+            ut[idx] = d[idx] * ut_fast
+        vals = [rho, ut[:, 0], ut[:, 1], ut[:, 2], p, Bv[:, 0], Bv[:, 1], Bv[:, 2]]
+        for f in range(NPRIM):
+            mb.view("prim", mb.prim, b, f)[...] = vals[f].reshape(shape)

@@ -74,6 +74,7 @@ class MBlock(ctypes.Structure):
     _fields_ = [("vs_offset", ctypes.c_longlong), ("vm_offset", ctypes.c_longlong),
                 ("vc_stride", ctypes.c_longlong), ("cg_offset", ctypes.c_longlong),
                 ("cp_offset", ctypes.c_longlong), ("ca_offset", ctypes.c_longlong),
+                ("cq_offset", ctypes.c_longlong), ("cf_offset", ctypes.c_longlong),
                 ("cc_stride", ctypes.c_longlong), ("ncx", ctypes.c_int), ("ncy", ctypes.c_int),
                 ("ncz", ctypes.c_int), ("ngv", ctypes.c_int), ("ngc", ctypes.c_int),
                 ("pad", ctypes.c_int)]
@@ -83,6 +84,15 @@ class Fluid(ctypes.Structure):
     """z4c_fluid of include/z4c_matter.h."""
     _fields_ = [("mhd", ctypes.c_int), ("gamma_ad", ctypes.c_double),
                 ("chi_floor", ctypes.c_double)]
+
+
+class C2PParams(ctypes.Structure):
+    """z4c_c2p_params of include/z4c_matter.h."""
+    _fields_ = [("mhd", ctypes.c_int), ("gamma_ad", ctypes.c_double),
+                ("chi_floor", ctypes.c_double), ("rho_atm", ctypes.c_double),
+                ("p_atm", ctypes.c_double), ("f_thr", ctypes.c_double),
+                ("ut_max", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int)]
 
 
 class Z4cError(RuntimeError):
@@ -133,8 +143,10 @@ def lib():
         L.z4c_metric_to_cc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.z4c_adm_sources.argtypes = [vp, ctypes.POINTER(Fluid), ctypes.c_int, vp, vp, vp, vp]
         L.z4c_sources_to_vc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.z4c_p2c.argtypes = [vp, ctypes.POINTER(C2PParams), ctypes.c_int, vp, vp, vp, vp]
+        L.z4c_c2p.argtypes = [vp, ctypes.POINTER(C2PParams), ctypes.c_int, vp, vp, vp, vp, vp]
         for name in ("z4c_mplan_create", "z4c_mplan_destroy", "z4c_metric_to_cc",
-                     "z4c_adm_sources", "z4c_sources_to_vc"):
+                     "z4c_adm_sources", "z4c_sources_to_vc", "z4c_p2c", "z4c_c2p"):
             getattr(L, name).restype = st
         for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params", "z4c_plan_set_halo",
                      "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
@@ -332,9 +344,26 @@ class MPlan:
         _check(lib().z4c_adm_sources(self._h, ctypes.byref(fl), int(ext), _ptr(geom), _ptr(prim),
                                      _ptr(adm), _stream(stream)))
 
+    def p2c(self, c, ext, geom, prim, cons, stream=None):
+        _check(lib().z4c_p2c(self._h, ctypes.byref(c), int(ext), _ptr(geom), _ptr(prim),
+                             _ptr(cons), _stream(stream)))
+
+    def c2p(self, c, ext, geom, cons, prim, status=None, stream=None):
+        _check(lib().z4c_c2p(self._h, ctypes.byref(c), int(ext), _ptr(geom), _ptr(cons),
+                             _ptr(prim), _ptr(status), _stream(stream)))
+
     def sources_to_vc(self, order, adm, matter, stream=None):
         _check(lib().z4c_sources_to_vc(self._h, int(order), _ptr(adm), _ptr(matter),
                                        _stream(stream)))
+
+
+def c2p_params(mhd=1, gamma_ad=2.0, chi_floor=1e-6, rho_atm=1e-13, p_atm=None, f_thr=1.0,
+               ut_max=20.0, tol=1e-15, max_iter=100) -> C2PParams:
+    """C2P parameters; p_atm defaults to the polytrope p = 100 rho^Gamma at rho_atm."""
+    if p_atm is None:
+        p_atm = 100.0 * rho_atm ** gamma_ad
+    return C2PParams(int(mhd), float(gamma_ad), float(chi_floor), float(rho_atm), float(p_atm),
+                     float(f_thr), float(ut_max), float(tol), int(max_iter))
 
 
 def mplan_for(mbatch, flags: int = 0) -> MPlan:

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     names = declared_functions("z4c.h")
     assert len(names) >= 15
     mnames = declared_functions("z4c_matter.h")
-    assert len(mnames) == 5
+    assert len(mnames) == 7
     for n in names + mnames:
         assert hasattr(L, n), n
 
@@ -48,8 +48,9 @@ def test_structure_layouts_match_header_sizes():
     assert W.BLOCK_DTYPE.itemsize == 72
     assert ctypes.sizeof(Z.RKCoeffs) == 56
     assert ctypes.sizeof(Z.Launch) == 20
-    assert ctypes.sizeof(Z.MBlock) == 80
-    assert W.MBLOCK_DTYPE.itemsize == 80
+    assert ctypes.sizeof(Z.MBlock) == 96
+    assert W.MBLOCK_DTYPE.itemsize == 96
+    assert ctypes.sizeof(Z.C2PParams) == 72
     assert ctypes.sizeof(Z.Fluid) == 24
 
 
