@@ -73,6 +73,8 @@ def parse():
                          "--steps launches of RK4 stage 2 in the autotuned configuration")
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="oracle sample size (0: the whole level set)")
+    ap.add_argument("--matter-only", action="store_true",
+                    help="only the matter-coupling and primitive-recovery kernels (one JSON line)")
     ap.add_argument("--table", action="store_true",
                     help="instead of the benchmark line: GPU FP64 / FP32 throughput of every "
                          "workload configuration and the oracle on 1 and on all host threads "
@@ -97,6 +99,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile:
         profile_run(args.steps, stream)
+        return
+    if args.matter_only:
+        print(json.dumps(matter_coupling(stream, args.steps)), flush=True)
         return
     if args.table:
         print(json.dumps(config_table(stream, max(args.steps, 20), args.warmup)), flush=True)
@@ -386,7 +391,8 @@ def matter_coupling(stream, reps):
             "adm_sources": 8 * (7 + 8 + 10) * ncs,
             "sources_to_vc": 8 * (10 * ncs + 10 * nv)}
     res = {"workload": mb.name + "; metric order 4 to the cells and 3 ghost layers, GRMHD "
-                                 "sources (Gamma = 2), sources order 6 to the vertices",
+                                 "sources (Gamma = 2), sources order 6 to the vertices; "
+                                 "primitive recovery (ideal gas, Gamma = 2) on the same cells",
            "cells": mb.ncells, "vertices": nv}
 
     def timed(fn):
@@ -410,6 +416,25 @@ def matter_coupling(stream, reps):
     med, mn = timed(lambda: [fn() for fn in calls.values()])
     res["chain"] = {"ms": (med, mn), "vertices_per_s": nv / (med * 1e-3),
                     "hbm_frac": sum(algo.values()) / (med * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # primitive recovery at the cells and their 3 ghost layers: conservatives
+    # of the level set's primitives (z4c_p2c), then z4c_c2p (the generator's
+    # vacuum cells become atmosphere on the first call; repeated calls find
+    # the same state)
+    c = Z.c2p_params(mhd=1, gamma_ad=2.0, rho_atm=1e-12)
+    cons = torch.zeros(mb.cons.size, dtype=torch.float64, device="cuda:0")
+    out = torch.zeros(mb.prim.size, dtype=torch.float64, device="cuda:0")
+    status = torch.zeros(mb.status.size, dtype=torch.int32, device="cuda:0")
+    algo_p2c = 8 * (7 + 8 + 8) * ncs
+    algo_c2p = (8 * (7 + 8 + 8) + 4) * ncs
+    for name, fn, nb in (("p2c", lambda: plan.p2c(c, 3, geom, prim, cons, stream=stream), algo_p2c),
+                         ("c2p", lambda: plan.c2p(c, 3, geom, cons, out, status, stream=stream),
+                          algo_c2p)):
+        med, mn = timed(fn)
+        gbs = nb / (med * 1e-3) / 1e9
+        res[name] = {"ms": (med, mn), "algorithmic_bytes": nb, "achieved_gbs": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS, "cells_per_s": ncs / (med * 1e-3)}
+    st = status.cpu().numpy()
+    res["c2p"]["status_counts"] = {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}
     log(f"[bench] matter coupling: {res}")
     plan.close()
     return res
