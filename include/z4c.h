@@ -124,7 +124,9 @@ typedef struct z4c_plan z4c_plan;
 /* Create a plan for `nblocks` blocks described by the HOST array `blocks`
  * (copied).  Validates every block (sizes, spacings, ghosts >= fd_order/2+1,
  * offsets >= 0) and the parameters, builds tile lists and uploads them to the
- * current HIP device.  *out receives the plan (NULL on error). */
+ * current HIP device.  *out receives the plan (NULL on error).  A block of
+ * 2^29 or more stored points ((nx+2ng)(ny+2ng)(nz+2ng)) is Z4C_ENOTSUP: the
+ * kernels address a block's points as 32-bit byte offsets. */
 z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, int nblocks,
                            int flags, z4c_plan **out);
 z4c_status z4c_plan_destroy(z4c_plan *plan);
@@ -180,7 +182,10 @@ z4c_status z4c_rk_stage(z4c_plan *plan, const double *u0_in, double *u0_out, dou
  * M_i (conformal form), Theta, Z^i = (Gt^i - Gt_d^i)/2 at interior points into
  * `cons` (constraint layout, may be NULL) and per-block norms into `norms`
  * (device, nblocks*16 doubles: for field q, [b*16+2q] = sum |c| dV and
- * [b*16+2q+1] = sum c^2 dV, dV = dx dy dz), summed in a fixed order. */
+ * [b*16+2q+1] = sum c^2 dV, dV = dx dy dz), summed in a fixed order.
+ * Needs offset + 22*field_stride < 2^32 for every block (Z4C_ENOTSUP
+ * otherwise: the constraint kernel addresses its halo from the array base
+ * with 32-bit element offsets). */
 z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter,
                            double *cons, double *norms, void *stream);
 

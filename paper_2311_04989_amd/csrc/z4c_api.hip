@@ -111,9 +111,12 @@ z4c_status check_block(const z4c_block &b, int idx, int fd_order)
     }
     const long long ex = b.nx + 2LL * b.ng, ey = b.ny + 2LL * b.ng, ez = b.nz + 2LL * b.ng;
     const long long npts = ex * ey * ez;
-    if (npts > INT_MAX) {
-        std::snprintf(buf, sizeof buf, "block %d: more than 2^31-1 stored points", idx);
-        return fail(Z4C_EINVAL, buf);
+    if (npts >= (1LL << 29)) {
+        // the kernels address a block's points as 32-bit byte offsets from
+        // the block's field base
+        std::snprintf(buf, sizeof buf, "block %d: %lld stored points; at most 2^29 - 1 are "
+                      "supported", idx, npts);
+        return fail(Z4C_ENOTSUP, buf);
     }
     if (b.offset < 0 || b.moffset < 0 || b.coffset < 0 || b.field_stride < npts) {
         std::snprintf(buf, sizeof buf,
@@ -843,6 +846,9 @@ z4c_status z4c_constraints(z4c_plan *P, const double *u, const double *matter, d
         return fail(Z4C_EINVAL, "outputs must not alias u or each other");
     if (!aligned8(u) || !aligned8(cons) || !aligned8(norms) || !aligned8(matter))
         return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (!P->offsets32)
+        return fail(Z4C_ENOTSUP, "constraints need offset + 22*field_stride < 2^32 for every "
+                                 "block (32-bit element offsets from the state array base)");
     z4c_status st = need_device(P);
     if (st != Z4C_OK)
         return st;

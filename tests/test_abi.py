@@ -252,3 +252,30 @@ def test_strerror_names_every_status():
     L = Z.lib()
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.z4c_strerror(s) and L.z4c_strerror(s) != b"unknown status"
+
+
+def test_size_limits_of_32_bit_addressing():
+    """Blocks of 2^29 or more stored points, and constraints over arrays whose
+    element offsets exceed 32 bits, are refused before anything runs."""
+    p = Z.make_params(W.Params(fd_order=6))
+    big = np.zeros(1, dtype=W.BLOCK_DTYPE)
+    n = 812                                   # (812 + 8)^3 = 551,368,000 >= 2^29
+    big[0] = (0, 0, 0, (n + 8) ** 3, n, n, n, 4, 1.0, 1.0, 1.0)
+    with pytest.raises(Z.Z4cError) as e:
+        Z.Plan(p, Z.make_blocks(big), Z.PLAN_NO_DEVICE)
+    assert e.value.status == Z.ENOTSUP
+    ok = big.copy()
+    ok[0]["nx"] = ok[0]["ny"] = ok[0]["nz"] = 800  # 808^3 = 527,514,112 < 2^29
+    ok[0]["field_stride"] = 808 ** 3
+    Z.Plan(p, Z.make_blocks(ok), Z.PLAN_NO_DEVICE).close()
+    far = np.zeros(2, dtype=W.BLOCK_DTYPE)
+    far[0] = (0, 0, 0, 24 ** 3, 16, 16, 16, 4, 1.0, 1.0, 1.0)
+    far[1] = (1 << 32, 0, 0, 24 ** 3, 16, 16, 16, 4, 1.0, 1.0, 1.0)
+    plan = Z.Plan(p, Z.make_blocks(far), Z.PLAN_NO_DEVICE)
+    with pytest.raises(Z.Z4cError) as e:
+        plan.constraints(8, None, 16, 24)
+    assert e.value.status == Z.ENOTSUP
+    with pytest.raises(Z.Z4cError) as e:
+        plan.set_halo(Z.GHOST_PERIODIC)
+    assert e.value.status == Z.ENOTSUP
+    plan.close()
