@@ -367,44 +367,48 @@ __global__ void __launch_bounds__(PNT) p2c_kernel(const C2PArgs a)
         o[i * fs] = q[i];
 }
 
-// Primitive recovery of one cell: the master function f(mu) = mu - mu_hat(mu)
-// of Kastaun, Kalinani & Ciolfi in mu = 1 / (h W), with the normalised
-// conservatives q = tau / D, r_i = S_i / D, b^i = B^i / sqrt(D) (all
-// undensitised):
+// Primitive recovery of one cell: the master function of Kastaun, Kalinani &
+// Ciolfi in mu = 1 / (h W), with the normalised conservatives q = tau / D,
+// r_i = S_i / D, b^i = B^i / sqrt(D) (all undensitised):
 //   x = 1 / (1 + mu b^2),  rbar^2 = x^2 r^2 + mu x (1 + x) (r.b)^2,
 //   qbar = q - b^2/2 - mu^2 x^2 (b^2 r^2 - (r.b)^2) / 2,
 //   v^2 = min(mu^2 rbar^2, vmax^2),  W = 1 / sqrt(1 - v^2),  rho = D / W,
 //   eps = max(W (qbar - mu rbar^2) + v^2 W^2 / (1 + W), 0),
 //   a = p / (rho (1 + eps)),  h = (1 + eps)(1 + a),
-//   nu = max(h / W, (1 + a)(1 + qbar - mu rbar^2)),  mu_hat = 1 / (nu + mu rbar^2).
+//   nu = max(h / W, (1 + a)(1 + qbar - mu rbar^2)),  mu_hat = 1 / (nu + mu rbar^2),
+//   f(mu) = mu - mu_hat(mu).
+// For the ideal gas p = (Gamma - 1) rho eps this reduces exactly to
+//   eps = max(W (qbar - mu rbar^2 + 1) - 1, 0)   (v^2 W^2 / (1 + W) = W - 1),
+//   h = 1 + Gamma eps,  nu = h / W            (the two branches of the max
+//   coincide unless eps is clamped, when h / W is the larger),
+// and, nu + mu rbar^2 being positive, the root and the sign of f are those
+// of g(mu) = mu (nu + mu rbar^2) - 1, which needs no division.
 struct Master {
-    double D, q, r2, b2, rb2, gm1, vmax2;
+    double q, r2, b2, rb2, gam, vmax2;
     __device__ __forceinline__ double x(double mu) const { return 1.0 / (1.0 + mu * b2); }
     __device__ __forceinline__ double rbar2(double mu) const
     {
         const double xx = x(mu);
         return r2 * xx * xx + mu * xx * (1.0 + xx) * rb2;
     }
+    // g(mu); W and eps of the estimate
     __device__ __forceinline__ double f(double mu, double &W, double &eps) const
     {
         const double xx = x(mu);
         const double rb = r2 * xx * xx + mu * xx * (1.0 + xx) * rb2;
         const double qb = q - 0.5 * b2 - 0.5 * mu * mu * xx * xx * (b2 * r2 - rb2);
         const double v2 = fmin(mu * mu * rb, vmax2);
-        W = 1.0 / sqrt(1.0 - v2);
-        const double rho = D / W;
-        const double e = W * (qb - mu * rb) + v2 * W * W / (1.0 + W);
+        const double iW = sqrt(1.0 - v2);
+        W = 1.0 / iW;
+        const double e = W * (qb - mu * rb + 1.0) - 1.0;
         eps = e > 0.0 ? e : 0.0;
-        const double pr = gm1 * rho * eps;
-        const double aa = pr / (rho * (1.0 + eps));
-        const double h = (1.0 + eps) * (1.0 + aa);
-        const double nu = fmax(h / W, (1.0 + aa) * (1.0 + qb - mu * rb));
-        return mu - 1.0 / (nu + mu * rb);
+        const double nu = (1.0 + gam * eps) * iW;
+        return mu * (nu + mu * rb) - 1.0;
     }
 };
 
 // Illinois iterations for a sign change of fn on [lo, hi] (fn(lo) < 0 <=
-// fn(hi)), every fourth step a bisection (the bracket shrinks whatever fn
+// fn(hi)), every eighth step a bisection (the bracket shrinks whatever fn
 // does); converged when the bracket is narrower than tol * hi or one ulp;
 // returns false after max_iter steps without convergence.
 template <typename Fn>
@@ -414,7 +418,7 @@ __device__ __forceinline__ bool illinois(Fn fn, double lo, double hi, double flo
     int side = 0;
     for (int it = 0; it < max_iter; ++it) {
         double m = (lo * fhi - hi * flo) / (fhi - flo);
-        if (!(m > lo && m < hi) || (it & 3) == 3)
+        if (!(m > lo && m < hi) || (it & 7) == 7)
             m = 0.5 * (lo + hi);
         if (!(m > lo && m < hi)) {
             root = m;
@@ -490,13 +494,12 @@ __global__ void __launch_bounds__(PNT) c2p_kernel(const C2PArgs a)
         double bl[3];
         lower(gam, bu, bl);
         Master M;
-        M.D = D;
         M.q = tau * iD;
         M.r2 = rl[0] * ru[0] + rl[1] * ru[1] + rl[2] * ru[2];
         M.b2 = bl[0] * bu[0] + bl[1] * bu[1] + bl[2] * bu[2];
         const double rb = rl[0] * bu[0] + rl[1] * bu[1] + rl[2] * bu[2];
         M.rb2 = rb * rb;
-        M.gm1 = a.gm1;
+        M.gam = a.gm1 + 1.0;
         M.vmax2 = a.vmax2;
         // bracket [0, mu+]: mu+ is the root of mu sqrt(1 + rbar^2(mu)) - 1
         // (minimum enthalpy 1) when it lies below 1
@@ -514,8 +517,8 @@ __global__ void __launch_bounds__(PNT) c2p_kernel(const C2PArgs a)
             const double f0 = fm(0.0), f1 = fm(mup);
             if (f0 < 0.0 && f1 >= 0.0)
                 ok = illinois(fm, 0.0, mup, f0, f1, a.tol, a.max_iter, mu);
-            else if (f0 < 0.0 && f1 >= -1e-12 * mup)
-                mu = mup;   // cold gas (h = 1): the root is mu+ itself, f(mu+) = 0 up to rounding
+            else if (f0 < 0.0 && f1 >= -1e-12)
+                mu = mup;   // cold gas (h = 1): the root is mu+ itself, g(mu+) = 0 up to rounding
             else
                 ok = false;
         }
