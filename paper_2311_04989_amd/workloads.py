@@ -690,3 +690,33 @@ def c2p_states(mb: MatterBatch, rng, wmax=10.0, mag=10.0, n_atm=0, n_fast=0, ut_
         vals = [rho, ut[:, 0], ut[:, 1], ut[:, 2], p, Bv[:, 0], Bv[:, 1], Bv[:, 2]]
         for f in range(NPRIM):
             mb.view("prim", mb.prim, b, f)[...] = vals[f].reshape(shape)
+
+
+def refined_pair(seed: int = 0, n_c: int = 24, n_f: int = 16, ng: int = 4, dx_c: float = 1.0,
+                 c0=(4, 4, 4), nfine: int = 2, fill=None):
+    """A coarse block and `nfine` fine blocks (spacing dx_c / 2) side by side
+    along x inside it: fine block m has its vertex 0 on coarse vertex
+    (c0[0] + m (n_f / 2), c0[1], c0[2]).  Fields: `fill(X, Y, Z, f)` at
+    every stored point (default: smooth seeded trigonometric data).
+    Returns the batch and the c0 of every fine block."""
+    rng = np.random.default_rng(SEED_BASE + 2000 + seed)
+    blocks = [Block(n_c, n_c, n_c, ng, dx_c, dx_c, dx_c)]
+    origins = []
+    for m in range(nfine):
+        o = (c0[0] + m * (n_f // 2), c0[1], c0[2])
+        origins.append(o)
+        blocks.append(Block(n_f, n_f, n_f, ng, dx_c / 2, dx_c / 2, dx_c / 2,
+                            x0=o[0] * dx_c, y0=o[1] * dx_c, z0=o[2] * dx_c))
+    bt = Batch(blocks)
+    a = rng.uniform(0.1, 0.4, size=(NF, 3))
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=NF)
+    for b, blk in enumerate(bt.blocks):
+        X, Y, Z = blk.coords()
+        for f in range(NF):
+            if fill is None:
+                v = np.sin(a[f, 0] * X + ph[f]) * np.cos(a[f, 1] * Y) + np.cos(a[f, 2] * Z + ph[f])
+            else:
+                v = fill(X, Y, Z, f)
+            bt.view(bt.u, b, f)[...] = v
+    bt.name = f"coarse {n_c}^3 + {nfine} fine {n_f}^3 blocks"
+    return bt, origins
