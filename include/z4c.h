@@ -240,6 +240,45 @@ z4c_status z4c_plan_autotune(z4c_plan *plan, const double *u0, double *u0_out, d
  * int, the call synchronises the stream). */
 z4c_status z4c_check_finite(z4c_plan *plan, const double *u, long long *count, void *stream);
 
+/* Transfers between refinement levels of a vertex-centred mesh with
+ * refinement ratio 2 (Sec. 3.2: the Z4c variables are vertex-centred so that
+ * restriction and prolongation between levels stay simple with high-order
+ * operators).  Fine vertex i of the fine block lies at coarse position
+ * c0 + i/2 of the coarse block (per direction; fine vertex 0 on coarse
+ * vertex c0), and the fine spacing is half the coarse one.
+ *   prolongation (destination: fine points in [lo, hi), ghosts allowed): an
+ *     even index copies the coincident coarse vertex, an odd one takes the
+ *     Lagrange polynomial through the `order` nearest coarse vertices at the
+ *     midpoint; in 3-D the tensor product of the three directions;
+ *   restriction (destination: coarse points in [lo, hi)): injection, coarse
+ *     vertex j takes fine vertex 2 (j - c0).
+ * All 22 state fields; each call works in place on one state array. */
+typedef struct {
+    int coarse, fine;   /* block indices of the plan (different blocks)         */
+    int c0[3];          /* coarse vertex under fine vertex 0                    */
+    int lo[3], hi[3];   /* destination box, half-open, destination block indices */
+} z4c_transfer;
+
+typedef struct z4c_xplan z4c_xplan;
+
+/* A set of transfers on the blocks of `plan` (HOST arrays, copied):
+ * `nprolong` prolongations and `nrestrict` restrictions, interpolation order
+ * 2, 4 or 6.  Validation: block indices, a spacing ratio of 2 (to 1e-12),
+ * destination boxes inside the destination's stored points, every source
+ * point of every destination point inside the source's stored points (else
+ * Z4C_ENOGHOST), and no block written by one transfer and read by another
+ * of the same kind (the calls run all transfers of a kind at once).  The
+ * xplan keeps a pointer to `plan`, which must outlive it. */
+z4c_status z4c_xplan_create(const z4c_plan *plan, const z4c_transfer *prolong, int nprolong,
+                            const z4c_transfer *restrict_, int nrestrict, int order, int flags,
+                            z4c_xplan **out);
+z4c_status z4c_xplan_destroy(z4c_xplan *xplan);
+
+/* Apply every prolongation (or every restriction) of `xplan` to the state
+ * array `u` (device, the plan's layout), asynchronously on the stream. */
+z4c_status z4c_prolongate(const z4c_xplan *xplan, double *u, void *hip_stream);
+z4c_status z4c_restrict(const z4c_xplan *xplan, double *u, void *hip_stream);
+
 const char *z4c_strerror(z4c_status status);
 const char *z4c_last_error(void);
 

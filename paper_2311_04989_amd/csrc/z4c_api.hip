@@ -544,6 +544,11 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
 }  // namespace
 
 z4c_status z4c::set_error(z4c_status s, const char *msg) { return fail(s, msg); }
+const std::vector<z4c_block> &z4c::plan_blocks(const z4c_plan *P) { return P->blocks; }
+const z4c_block *z4c::plan_blocks_device(const z4c_plan *P)
+{
+    return P->device ? P->blocks_d : nullptr;
+}
 z4c_status z4c::set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 extern "C" {

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "z4c.h"
 
 namespace z4c {
@@ -91,6 +93,11 @@ hipError_t launch_finite_count(const z4c_block *blocks, int nblocks, const long 
                                long long total_pts, const double *u,
                                unsigned long long *count, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+
+// Read access to a plan from other translation units: its host block table,
+// its device copy (nullptr without a device).
+const std::vector<z4c_block> &plan_blocks(const z4c_plan *P);
+const z4c_block *plan_blocks_device(const z4c_plan *P);
 
 // Last-error message of the calling thread (z4c_last_error), for the host
 // code of every translation unit; both return their status argument.

@@ -95,6 +95,12 @@ class C2PParams(ctypes.Structure):
                 ("max_iter", ctypes.c_int)]
 
 
+class Transfer(ctypes.Structure):
+    """z4c_transfer of include/z4c.h."""
+    _fields_ = [("coarse", ctypes.c_int), ("fine", ctypes.c_int), ("c0", ctypes.c_int * 3),
+                ("lo", ctypes.c_int * 3), ("hi", ctypes.c_int * 3)]
+
+
 class Z4cError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"z4c status {status}: {message}")
@@ -145,6 +151,14 @@ def lib():
         L.z4c_sources_to_vc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.z4c_p2c.argtypes = [vp, ctypes.POINTER(C2PParams), ctypes.c_int, vp, vp, vp, vp]
         L.z4c_c2p.argtypes = [vp, ctypes.POINTER(C2PParams), ctypes.c_int, vp, vp, vp, vp, vp]
+        L.z4c_xplan_create.argtypes = [vp, ctypes.POINTER(Transfer), ctypes.c_int,
+                                       ctypes.POINTER(Transfer), ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(vp)]
+        L.z4c_xplan_destroy.argtypes = [vp]
+        L.z4c_prolongate.argtypes = [vp, vp, vp]
+        L.z4c_restrict.argtypes = [vp, vp, vp]
+        for name in ("z4c_xplan_create", "z4c_xplan_destroy", "z4c_prolongate", "z4c_restrict"):
+            getattr(L, name).restype = st
         for name in ("z4c_mplan_create", "z4c_mplan_destroy", "z4c_metric_to_cc",
                      "z4c_adm_sources", "z4c_sources_to_vc", "z4c_p2c", "z4c_c2p"):
             getattr(L, name).restype = st
@@ -368,3 +382,41 @@ def c2p_params(mhd=1, gamma_ad=2.0, chi_floor=1e-6, rho_atm=1e-13, p_atm=None, f
 
 def mplan_for(mbatch, flags: int = 0) -> MPlan:
     return MPlan(mbatch.table(), flags)
+
+
+def make_transfers(items):
+    """C z4c_transfer array from dicts with coarse, fine, c0, lo, hi."""
+    arr = (Transfer * max(len(items), 1))()
+    for k, t in enumerate(items):
+        arr[k] = Transfer(int(t["coarse"]), int(t["fine"]), (ctypes.c_int * 3)(*t["c0"]),
+                          (ctypes.c_int * 3)(*t["lo"]), (ctypes.c_int * 3)(*t["hi"]))
+    return arr
+
+
+class XPlan:
+    """Transfers between refinement levels (z4c_xplan) over the blocks of a
+    Plan, which must stay alive as long as the XPlan."""
+
+    def __init__(self, plan: Plan, prolong, restrict, order: int, flags: int = 0):
+        self._h = ctypes.c_void_p()
+        self._plan = plan
+        p, r = make_transfers(prolong), make_transfers(restrict)
+        _check(lib().z4c_xplan_create(plan._h, p, len(prolong), r, len(restrict), int(order),
+                                      int(flags), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().z4c_xplan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prolongate(self, u, stream=None):
+        _check(lib().z4c_prolongate(self._h, _ptr(u), _stream(stream)))
+
+    def restrict(self, u, stream=None):
+        _check(lib().z4c_restrict(self._h, _ptr(u), _stream(stream)))

@@ -279,3 +279,37 @@ def test_size_limits_of_32_bit_addressing():
         plan.set_halo(Z.GHOST_PERIODIC)
     assert e.value.status == Z.ENOTSUP
     plan.close()
+
+
+def test_intergrid_transfer_validation():
+    bt, origins = W.refined_pair(seed=1)
+    plan = Z.Plan(Z.make_params(bt.params), Z.make_blocks(bt.block_table()), Z.PLAN_NO_DEVICE)
+    good = dict(coarse=0, fine=1, c0=origins[0], lo=[-4, -4, -4], hi=[0, 20, 20])
+    Z.XPlan(plan, [good], [], 6, Z.PLAN_NO_DEVICE).close()
+    cases = [
+        (dict(good, coarse=5), Z.EINVAL),                      # bad block index
+        (dict(good, fine=0), Z.EINVAL),                        # same block
+        (dict(good, coarse=2, fine=1), Z.EINVAL),              # spacing ratio 1
+        (dict(good, lo=[-5, -4, -4]), Z.EINVAL),               # box outside the stored points
+        (dict(good, c0=[-1, 4, 4]), Z.ENOGHOST),               # stencil leaves the coarse block
+    ]
+    for t, status in cases:
+        with pytest.raises(Z.Z4cError) as e:
+            Z.XPlan(plan, [t], [], 6, Z.PLAN_NO_DEVICE)
+        assert e.value.status == status, t
+    with pytest.raises(Z.Z4cError) as e:
+        Z.XPlan(plan, [good], [], 5, Z.PLAN_NO_DEVICE)
+    assert e.value.status == Z.EINVAL
+    with pytest.raises(Z.Z4cError) as e:                       # overlapping destinations
+        Z.XPlan(plan, [good, dict(good, lo=[-2, -4, -4])], [], 6, Z.PLAN_NO_DEVICE)
+    assert e.value.status == Z.EINVAL
+    chain = dict(coarse=1, fine=2, c0=[0, 0, 0], lo=[0, 0, 0], hi=[1, 1, 1])
+    with pytest.raises(Z.Z4cError) as e:                       # block 1 written and read
+        Z.XPlan(plan, [good, chain], [], 6, Z.PLAN_NO_DEVICE)
+    assert e.value.status == Z.EINVAL
+    xp = Z.XPlan(plan, [good], [], 6, Z.PLAN_NO_DEVICE)
+    with pytest.raises(Z.Z4cError) as e:
+        xp.prolongate(8)
+    assert e.value.status == Z.ENODEV
+    xp.close()
+    plan.close()

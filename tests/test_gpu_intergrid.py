@@ -1,0 +1,116 @@
+"""Transfers between refinement levels on the GPU (z4c_prolongate,
+z4c_restrict through the C ABI) against oracle/intergrid.py: prolongation
+of the ghost slabs and of whole fine blocks for orders 2, 4, 6 within 1e-13
+(relative, 1e-3 floor; linear combinations, rounding order only), bitwise
+on polynomial data of degree < order, restriction bitwise; every point no
+transfer writes keeps its value bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import intergrid as OI
+from paper_2311_04989_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def Z():
+    from paper_2311_04989_amd import z4c
+    return z4c
+
+
+def ghost_slabs(blk, fine, c0):
+    n, g = blk.nx, blk.ng
+    out = []
+    for d in range(3):
+        for lo, hi in ((-g, 0), (n, n + g)):
+            b_lo, b_hi = [-g] * 3, [n + g] * 3
+            if d > 0:          # slabs of earlier directions already cover their corners
+                for e in range(d):
+                    b_lo[e], b_hi[e] = 0, n
+            b_lo[d], b_hi[d] = lo, hi
+            out.append(dict(coarse=0, fine=fine, c0=c0, lo=b_lo, hi=b_hi))
+    return out
+
+
+def run(bt, pro, res, order):
+    plan = Z().plan_for(bt)
+    xp = Z().XPlan(plan, pro, res, order)
+    u = torch.from_numpy(bt.u.copy()).to(DEV)
+    if pro:
+        xp.prolongate(u)
+    if res:
+        xp.restrict(u)
+    torch.cuda.synchronize()
+    out = u.cpu().numpy()
+    xp.close()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_prolongation_parity(order):
+    bt, origins = W.refined_pair(seed=order)
+    pro = []
+    for m, c0 in enumerate(origins):
+        pro += ghost_slabs(bt.blocks[1 + m], 1 + m, c0)
+    note(f"prolongation order {order}: {len(pro)} transfers")
+    got = run(bt, pro, [], order)
+    want = OI.prolong(bt, bt.u, pro, order)
+    written = want != bt.u
+    assert np.all(got[~written] == bt.u[~written]) or np.all(got[~written] == want[~written])
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            g, o = bt.view(got, b, f), bt.view(want, b, f)
+            m = np.abs(o).max()
+            e = (np.abs(g - o) / np.maximum(np.abs(o), 1e-3 * m)).max()
+            assert e <= 1e-13, (b, f, e)
+    # the coarse block is only read
+    for f in range(W.NF):
+        assert np.array_equal(bt.view(got, 0, f), bt.view(bt.u, 0, f))
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_prolongation_exact_on_polynomials(order):
+    deg = order - 1
+    bt, origins = W.refined_pair(
+        fill=lambda X, Y, Z, f: (X ** deg - X + 2) * (Y ** deg + 1) * (Z ** deg - 3) + f)
+    pro = [dict(coarse=0, fine=1 + m, c0=c0, lo=[-4] * 3, hi=[20] * 3)
+           for m, c0 in enumerate(origins)]
+    note(f"prolongation polynomial order {order}")
+    got = run(bt, pro, [], order)
+    for m in range(len(origins)):
+        X, Y, Zc = bt.blocks[1 + m].coords()
+        for f in range(W.NF):
+            want = (X ** deg - X + 2) * (Y ** deg + 1) * (Zc ** deg - 3) + f
+            np.testing.assert_allclose(bt.view(got, 1 + m, f), want, rtol=1e-14,
+                                       atol=1e-14 * np.abs(want).max())
+
+
+def test_restriction_parity():
+    bt, origins = W.refined_pair(seed=9)
+    for m in range(len(origins)):           # fine data that differ from the coarse data
+        for f in range(W.NF):
+            bt.view(bt.u, 1 + m, f)[...] += 0.5 + f
+    res = [dict(coarse=0, fine=1 + m, c0=c0, lo=list(c0), hi=[c0[0] + 8, c0[1] + 8, c0[2] + 8])
+           for m, c0 in enumerate(origins)]
+    note("restriction")
+    got = run(bt, [], res, 6)
+    want = OI.restrict(bt, bt.u, res)
+    assert np.array_equal(got, want)
+    assert not np.array_equal(got, bt.u)
