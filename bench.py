@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--no-matter", action="store_true",
                     help="skip the matter-coupling kernels (metric to cells, ADM sources, "
                          "sources to vertices)")
+    ap.add_argument("--no-intergrid", action="store_true",
+                    help="skip the transfers between refinement levels")
+    ap.add_argument("--intergrid-only", action="store_true",
+                    help="only the transfers between refinement levels (one JSON line)")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration), then "
                          "--steps launches of RK4 stage 2 in the autotuned configuration")
@@ -102,6 +106,9 @@ def main():
         return
     if args.matter_only:
         print(json.dumps(matter_coupling(stream, args.steps)), flush=True)
+        return
+    if args.intergrid_only:
+        print(json.dumps(intergrid_transfers(stream, args.steps)), flush=True)
         return
     if args.table:
         print(json.dumps(config_table(stream, max(args.steps, 20), args.warmup)), flush=True)
@@ -257,6 +264,8 @@ def main():
         out["batching"] = batching(stream, args.steps)
     if not args.no_matter:
         out["matter_coupling"] = matter_coupling(stream, args.steps)
+    if not args.no_intergrid:
+        out["intergrid"] = intergrid_transfers(stream, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
@@ -438,6 +447,72 @@ def matter_coupling(stream, reps):
     log(f"[bench] matter coupling: {res}")
     plan.close()
     return res
+
+
+def _footprint(t, order, prolong):
+    """Stored source points one transfer reads (the product over directions of
+    the index range its destination box reaches)."""
+    n = 1
+    for d in range(3):
+        idx = set()
+        for i in range(t["lo"][d], t["hi"][d]):
+            if not prolong:
+                idx.add(2 * (i - t["c0"][d]))
+            elif i % 2 == 0:
+                idx.add(t["c0"][d] + i // 2)
+            else:
+                left = t["c0"][d] + (i - 1) // 2
+                idx.update(range(left - (order // 2 - 1), left + order // 2 + 1))
+        n *= len(idx)
+    return n
+
+
+def intergrid_transfers(stream, reps, order=6):
+    """Transfers of a level jump at scale (64 coarse and 512 fine blocks of
+    16^3 + 4 ghosts): prolongation (order 6) of the six face slabs of every
+    fine block, restriction (injection) of every fine block into its octant.
+    Algorithmic bytes of a transfer: its destination box written once and
+    the source points its box reaches read once (22 fields, FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    t0 = time.time()
+    bt, pro, res = W.level_jump()
+    log(f"[bench] intergrid: generated {bt.name} in {time.time() - t0:.1f}s")
+    plan = Z.plan_for(bt)
+    xp = Z.XPlan(plan, pro, res, order)
+    u = torch.from_numpy(bt.u).to("cuda:0")
+    box = lambda t: int(np.prod([h - l for l, h in zip(t["lo"], t["hi"])]))   # noqa: E731
+    npro = sum(box(t) for t in pro)
+    nres = sum(box(t) for t in res)
+    algo = {"prolongate": 8 * 22 * (npro + sum(_footprint(t, order, True) for t in pro)),
+            "restrict": 8 * 22 * (nres + sum(_footprint(t, order, False) for t in res))}
+    calls = {"prolongate": lambda: xp.prolongate(u, stream=stream),
+             "restrict": lambda: xp.restrict(u, stream=stream)}
+    out = {"workload": bt.name + f"; prolongation order {order}, restriction by injection",
+           "prolongated_points": npro, "restricted_points": nres}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        gbs = algo[name] / (med * 1e-3) / 1e9
+        out[name] = {"ms": (med, float(np.min(ms))), "algorithmic_bytes": algo[name],
+                     "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    log(f"[bench] intergrid: {out}")
+    xp.close()
+    plan.close()
+    return out
 
 
 def host_info():

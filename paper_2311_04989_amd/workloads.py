@@ -720,3 +720,47 @@ def refined_pair(seed: int = 0, n_c: int = 24, n_f: int = 16, ng: int = 4, dx_c:
             bt.view(bt.u, b, f)[...] = v
     bt.name = f"coarse {n_c}^3 + {nfine} fine {n_f}^3 blocks"
     return bt, origins
+
+
+def level_jump(seed_offset: int = 7, ncoarse: int = 64, n: int = 16, ng: int = 4):
+    """Transfers of a level jump at scale: `ncoarse` coarse blocks of n^3 + ng
+    ghosts (spacing 1) and 8 fine blocks (spacing 1/2) per coarse block, fine
+    block k being octant k % 8 of coarse block k // 8.
+    * prolongation: every fine block receives its six face slabs (ng deep,
+      n x n across; the edges and corners left out so that no two boxes
+      meet), each from a coarse block drawn at random, whose vertex (4, 4, 4)
+      lies under fine vertex 0 (so an order-6 stencil stays inside the
+      coarse block's stored points);
+    * restriction: every fine block injects its even interior vertices into
+      its octant of its coarse block (coarse box 8 m .. 8 m + 8 per direction,
+      m the octant bit, when n = 16).
+    State: seeded uniform values in [-1, 1).  Returns (batch, prolongation
+    transfers, restriction transfers) as dicts with coarse, fine, c0, lo, hi."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    h = n // 2
+    blocks = [Block(n, n, n, ng, 1.0, 1.0, 1.0, x0=n * c, y0=0.0, z0=0.0)
+              for c in range(ncoarse)]
+    for k in range(8 * ncoarse):
+        p, o = divmod(k, 8)
+        m = (o & 1, (o >> 1) & 1, (o >> 2) & 1)
+        blocks.append(Block(n, n, n, ng, 0.5, 0.5, 0.5, x0=n * p + h * m[0], y0=h * m[1],
+                            z0=h * m[2]))
+    bt = Batch(blocks)
+    bt.u[:] = rng.uniform(-1.0, 1.0, size=bt.u.size)
+    pro, res = [], []
+    src = rng.integers(0, ncoarse, size=(8 * ncoarse, 6))
+    for k in range(8 * ncoarse):
+        fine = ncoarse + k
+        s = 0
+        for d in range(3):
+            for lo, hi in ((-ng, 0), (n, n + ng)):
+                b_lo, b_hi = [0] * 3, [n] * 3
+                b_lo[d], b_hi[d] = lo, hi
+                pro.append(dict(coarse=int(src[k, s]), fine=fine, c0=[4, 4, 4], lo=b_lo, hi=b_hi))
+                s += 1
+        p, o = divmod(k, 8)
+        c0 = [h * ((o >> d) & 1) for d in range(3)]
+        res.append(dict(coarse=p, fine=fine, c0=c0, lo=list(c0), hi=[c + h for c in c0]))
+    bt.name = (f"level jump: {ncoarse} coarse + {8 * ncoarse} fine blocks of {n}^3+{ng}g; "
+               f"{len(pro)} face slabs prolongated, {len(res)} octants restricted")
+    return bt, pro, res

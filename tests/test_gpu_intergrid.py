@@ -114,3 +114,41 @@ def test_restriction_parity():
     want = OI.restrict(bt, bt.u, res)
     assert np.array_equal(got, want)
     assert not np.array_equal(got, bt.u)
+
+
+def test_level_jump_at_scale_sampled():
+    """The measured workload (64 coarse + 512 fine blocks, 3072 face slabs of
+    order 6, 512 octants restricted), both calls in sequence as timed: a
+    seeded sample of 48 prolongation and 48 restriction transfers against
+    the oracle, and every fine interior point untouched."""
+    bt, pro, res = W.level_jump()
+    note(f"level jump at scale: {bt.name}")
+    plan = Z().plan_for(bt)
+    xp = Z().XPlan(plan, pro, res, 6)
+    u = torch.from_numpy(bt.u).to(DEV)
+    xp.prolongate(u)
+    xp.restrict(u)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    xp.close()
+    plan.close()
+    rng = np.random.default_rng(77)
+    sp = [pro[i] for i in rng.choice(len(pro), 48, replace=False)]
+    sr = [res[i] for i in rng.choice(len(res), 48, replace=False)]
+    want_p = OI.prolong(bt, bt.u, sp, 6)
+    want_r = OI.restrict(bt, bt.u, sr)
+    for t in sp:
+        fb, ng = t["fine"], bt.blocks[t["fine"]].ng
+        sl = tuple(slice(t["lo"][d] + ng, t["hi"][d] + ng) for d in (2, 1, 0))
+        for f in range(W.NF):
+            g, o = bt.view(got, fb, f)[sl], bt.view(want_p, fb, f)[sl]
+            assert np.abs(g - o).max() <= 1e-13 * max(np.abs(o).max(), 1.0), (t, f)
+    for t in sr:
+        cb, ng = t["coarse"], bt.blocks[t["coarse"]].ng
+        sl = tuple(slice(t["lo"][d] + ng, t["hi"][d] + ng) for d in (2, 1, 0))
+        for f in range(W.NF):
+            assert np.array_equal(bt.view(got, cb, f)[sl], bt.view(want_r, cb, f)[sl]), (t, f)
+    nc = 64
+    for b in range(nc, len(bt.blocks), 37):
+        for f in (0, 7, 21):
+            assert np.array_equal(bt.interior(got, b, f), bt.interior(bt.u, b, f))
