@@ -2,10 +2,15 @@
 // vertex-centred Z4c grid (ratio 2): prolongation coarse -> fine by
 // Lagrange interpolation and restriction fine -> coarse by injection
 // (Sec. 3.2: vertex-centred variables keep these operators simple at high
-// order).  One thread per destination point; transfers are located by a
-// binary search over the prefix sums of their box sizes; each point
-// gathers its 1 or `order` source points per direction (1 for an even fine
-// index, `order` for an odd one) for all 22 fields.
+// order).
+// Prolongation: the host cuts every destination box into tiles of at most
+// 16 x 16 x 4 fine points and records the coarse index range (footprint)
+// each tile reads; one workgroup per (tile, field) stages the footprint in
+// LDS and applies the three direction rules one after the other (x, then
+// y, then z; an even fine index copies, an odd one takes `order` taps), the
+// z pass writing the fine points to HBM.  Restriction: one thread per
+// (destination point, field), the transfer found by a binary search over the
+// prefix sums of the box sizes.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -14,14 +19,38 @@
 
 #include "z4c_internal.h"
 
+namespace z4c {
+namespace {
+
+// A tile of a prolongation box: fine points lo .. lo + n - 1 per direction
+// (index of the fine block, ghosts negative), the coarse points s0 ..
+// s0 + sn - 1 their stencils reach, and the order of the three direction
+// passes (dir[0] first).
+struct XTile {
+    int t;
+    int lo[3], n[3], s0[3], sn[3];
+    int dir[3];
+};
+static_assert(sizeof(XTile) == 64, "XTile layout");
+
+// LDS of a tile (doubles): A holds the footprint, then the second pass's
+// result; B the first pass's result.
+constexpr int XA = 2048, XB = 2048;
+
+}  // namespace
+}  // namespace z4c
+
 struct z4c_xplan {
     const z4c_plan *plan = nullptr;
     int order = 0;
     bool device = false;
     std::vector<z4c_transfer> pro, res;
+    std::vector<z4c::XTile> tiles;
+    long long lds_a = 0, lds_b = 0;   // LDS (doubles) of the largest tile
     z4c_transfer *pro_d = nullptr, *res_d = nullptr;
-    long long *pro_start_d = nullptr, *res_start_d = nullptr;   // prefix sums, n + 1
-    long long pro_total = 0, res_total = 0;
+    z4c::XTile *tiles_d = nullptr;
+    long long *res_start_d = nullptr;   // prefix sums of the restriction boxes, n + 1
+    long long res_total = 0;
 };
 
 namespace z4c {
@@ -58,53 +87,131 @@ __device__ __forceinline__ long long point_index(const z4c_block &B, int i, int 
     return (i + B.ng) + sx * ((j + B.ng) + sy * (long long)(k + B.ng));
 }
 
+// first coarse tap of fine index i (c0: coarse index of fine index 0)
 template <int O>
-__global__ void __launch_bounds__(256)
-prolong_kernel(const z4c_block *blocks, const z4c_transfer *tr, const long long *start, int n,
-               long long total, double *u)
+__device__ __forceinline__ int first_tap(int i, int c0)
 {
-    for (long long r = blockIdx.x * 256LL + threadIdx.x; r < total;
-         r += (long long)gridDim.x * 256) {
-        const int t = find_transfer(start, n, r);
-        const z4c_transfer T = tr[t];
-        const long long loc = r - start[t];
-        const int bx = T.hi[0] - T.lo[0], by = T.hi[1] - T.lo[1];
-        const int fi[3] = {T.lo[0] + (int)(loc % bx), T.lo[1] + (int)((loc / bx) % by),
-                           T.lo[2] + (int)(loc / ((long long)bx * by))};
-        // per direction: first coarse index, number of taps (1 or O)
-        int c[3], nt[3];
+    return (i & 1) == 0 ? c0 + (i >> 1) : c0 + ((i - 1) >> 1) - (O / 2 - 1);
+}
+
+// one direction rule at fine index i over values p[first * stride], ...
+template <int O>
+__device__ __forceinline__ double rule(const double *p, int first, int i, int stride)
+{
+    if ((i & 1) == 0)
+        return p[first * stride];
+    double s = 0.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if ((fi[d] & 1) == 0) {
-                c[d] = T.c0[d] + (fi[d] >> 1);
-                nt[d] = 1;
-            } else {
-                c[d] = T.c0[d] + ((fi[d] - 1) >> 1) - (O / 2 - 1);
-                nt[d] = O;
-            }
-        }
-        const z4c_block C = blocks[T.coarse];
-        const z4c_block F = blocks[T.fine];
-        const long long csx = C.nx + 2LL * C.ng, csy = C.ny + 2LL * C.ng;
-        const long long cbase = C.offset + point_index(C, c[0], c[1], c[2]);
-        const long long dst = F.offset + point_index(F, fi[0], fi[1], fi[2]);
-        for (int f = 0; f < NFIELD; ++f) {
-            const double *src = u + cbase + f * C.field_stride;
-            double s = 0.0;
-            for (int kz = 0; kz < nt[2]; ++kz) {
-                const double wz = nt[2] == 1 ? 1.0 : mid_weight<O>(kz);
-                for (int ky = 0; ky < nt[1]; ++ky) {
-                    const double wy = nt[1] == 1 ? 1.0 : mid_weight<O>(ky);
-                    const double *row = src + csx * (ky + csy * (long long)kz);
-                    double sx = 0.0;
-                    for (int kx = 0; kx < nt[0]; ++kx)
-                        sx += (nt[0] == 1 ? 1.0 : mid_weight<O>(kx)) * row[kx];
-                    s += wz * wy * sx;
-                }
-            }
-            u[dst + f * F.field_stride] = s;
+    for (int k = 0; k < O; ++k)
+        s += mid_weight<O>(k) * p[(first + k) * stride];
+    return s;
+}
+
+// e / d and e % d for e * d < 2^20 (every index and extent of a tile):
+// e * ceil(2^20 / d) / 2^20 errs by less than e / 2^20 < 1 / d.
+struct SmallDiv {
+    unsigned m, d;
+    __device__ explicit SmallDiv(unsigned d_) : m(((1u << 20) + d_ - 1) / d_), d(d_) {}
+    __device__ unsigned q(unsigned e) const { return (e * m) >> 20; }
+};
+
+// One direction pass (direction D) of a tile: `in` holds i0 x i1 x i2
+// values (x fastest); the result has T.n[D] points in direction D, written
+// to `out` (x fastest) or, for the last pass, to the fine block's points.
+// D is a template argument so that every index into the tile stays in
+// registers.
+template <int O, int D, bool LAST>
+__device__ __forceinline__ void dir_pass(const double *in, double *out, int i0, int i1, int i2,
+                                         const XTile &T, const z4c_transfer &R,
+                                         const z4c_block &F, double *dst)
+{
+    const int o0 = D == 0 ? T.n[0] : i0, o1 = D == 1 ? T.n[1] : i1, o2 = D == 2 ? T.n[2] : i2;
+    const int st1 = i0, st2 = i0 * i1;
+    const int std_ = D == 0 ? 1 : (D == 1 ? st1 : st2);
+    const SmallDiv d0(o0), d1(o1);
+    const unsigned total = o0 * o1 * o2;
+    constexpr int NK = (LAST ? 1024 : XA) / 256;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const unsigned e = threadIdx.x + 256u * k;
+        if (e < total) {
+            const unsigned r = d0.q(e), x = e - r * o0;
+            const unsigned z = d1.q(r), y = r - z * o1;
+            const int c = D == 0 ? (int)x : (D == 1 ? (int)y : (int)z);
+            const int i = T.lo[D] + c;
+            const int first = first_tap<O>(i, R.c0[D]) - T.s0[D];
+            const int base = (int)x + st1 * (int)y + st2 * (int)z + (first - c) * std_;
+            const double v = rule<O>(in + base, 0, i, std_);
+            if constexpr (LAST)
+                dst[point_index(F, T.lo[0] + (int)x, T.lo[1] + (int)y, T.lo[2] + (int)z)] = v;
+            else
+                out[e] = v;
         }
     }
+}
+
+template <int O, bool LAST>
+__device__ __forceinline__ void any_pass(int d, const double *in, double *out, int &i0, int &i1,
+                                         int &i2, const XTile &T, const z4c_transfer &R,
+                                         const z4c_block &F, double *dst)
+{
+    if (d == 0) {
+        dir_pass<O, 0, LAST>(in, out, i0, i1, i2, T, R, F, dst);
+        i0 = T.n[0];
+    } else if (d == 1) {
+        dir_pass<O, 1, LAST>(in, out, i0, i1, i2, T, R, F, dst);
+        i1 = T.n[1];
+    } else {
+        dir_pass<O, 2, LAST>(in, out, i0, i1, i2, T, R, F, dst);
+        i2 = T.n[2];
+    }
+}
+
+template <int O>
+__global__ void __launch_bounds__(256)
+prolong_kernel(const z4c_block *blocks, const z4c_transfer *tr, const XTile *tiles, int a_size,
+               double *u)
+{
+    extern __shared__ double lds[];
+    double *A = lds, *Bx = lds + a_size;
+    const XTile T = tiles[blockIdx.x];
+    const int f = blockIdx.y;
+    const z4c_transfer R = tr[T.t];
+    const z4c_block C = blocks[R.coarse];
+    const z4c_block F = blocks[R.fine];
+    const unsigned tid = threadIdx.x;
+    int i0 = T.sn[0], i1 = T.sn[1], i2 = T.sn[2];
+    // footprint -> A (x fastest): every load issued before the first LDS write
+    {
+        const SmallDiv ds0(i0), ds1(i1);
+        const long long csx = C.nx + 2LL * C.ng, csy = C.ny + 2LL * C.ng;
+        const double *src = u + C.offset + (long long)f * C.field_stride
+                          + point_index(C, T.s0[0], T.s0[1], T.s0[2]);
+        const unsigned ns = i0 * i1 * i2;
+        double v[XA / 256];
+#pragma unroll
+        for (int k = 0; k < XA / 256; ++k) {
+            const unsigned e = tid + 256u * k;
+            if (e < ns) {
+                const unsigned r = ds0.q(e), x = e - r * i0;
+                const unsigned z = ds1.q(r), y = r - z * i1;
+                v[k] = src[x + csx * (y + csy * (long long)z)];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < XA / 256; ++k) {
+            const unsigned e = tid + 256u * k;
+            if (e < ns)
+                A[e] = v[k];
+        }
+    }
+    __syncthreads();
+    double *dst = u + F.offset + (long long)f * F.field_stride;
+    any_pass<O, false>(T.dir[0], A, Bx, i0, i1, i2, T, R, F, dst);
+    __syncthreads();
+    any_pass<O, false>(T.dir[1], Bx, A, i0, i1, i2, T, R, F, dst);
+    __syncthreads();
+    any_pass<O, true>(T.dir[2], A, nullptr, i0, i1, i2, T, R, F, dst);
 }
 
 __global__ void __launch_bounds__(256)
@@ -124,8 +231,13 @@ restrict_kernel(const z4c_block *blocks, const z4c_transfer *tr, const long long
         const long long src = F.offset + point_index(F, 2 * (cj[0] - T.c0[0]),
                                                      2 * (cj[1] - T.c0[1]), 2 * (cj[2] - T.c0[2]));
         const long long dst = C.offset + point_index(C, cj[0], cj[1], cj[2]);
+        double v[NFIELD];   // every load issued before the first store
+#pragma unroll
         for (int f = 0; f < NFIELD; ++f)
-            u[dst + f * C.field_stride] = u[src + f * F.field_stride];
+            v[f] = u[src + f * F.field_stride];
+#pragma unroll
+        for (int f = 0; f < NFIELD; ++f)
+            u[dst + f * C.field_stride] = v[f];
     }
 }
 
@@ -218,6 +330,92 @@ std::vector<long long> prefix(const std::vector<z4c_transfer> &v)
     return s;
 }
 
+// coarse index range [s0, s0 + sn) the rule reaches from fine indices
+// lo .. lo + n - 1 (c0: coarse index of fine index 0)
+void footprint(int lo, int n, int c0, int order, int &s0, int &sn)
+{
+    int a = INT32_MAX, b = INT32_MIN;
+    for (int i = lo; i < lo + n; ++i) {
+        int first, last;
+        if (i % 2 == 0) {
+            first = last = c0 + i / 2;
+        } else {
+            const int left = c0 + (i - 1) / 2;   // i - 1 even
+            first = left - (order / 2 - 1);
+            last = left + order / 2;
+        }
+        a = std::min(a, first);
+        b = std::max(b, last);
+    }
+    s0 = a;
+    sn = b - a + 1;
+}
+
+// LDS (doubles) of a tile: a = footprint and second pass, b = first pass.
+void tile_lds(const XTile &T, long long &a, long long &b)
+{
+    long long dims[3] = {T.sn[0], T.sn[1], T.sn[2]};
+    const long long S = dims[0] * dims[1] * dims[2];
+    dims[T.dir[0]] = T.n[T.dir[0]];
+    b = dims[0] * dims[1] * dims[2];
+    dims[T.dir[1]] = T.n[T.dir[1]];
+    a = std::max(S, dims[0] * dims[1] * dims[2]);
+}
+
+// Cuts every prolongation box into tiles whose LDS needs fit XA and XB.
+std::vector<XTile> make_tiles(const std::vector<z4c_transfer> &v, int order)
+{
+    // footprint bound of n fine points: ceil(n / 2) - 1 + order
+    auto sb = [order](int n) { return (n + 1) / 2 + order; };
+    std::vector<XTile> out;
+    for (size_t t = 0; t < v.size(); ++t) {
+        const z4c_transfer &R = v[t];
+        const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1], bz = R.hi[2] - R.lo[2];
+        if (bx == 0 || by == 0 || bz == 0)
+            continue;
+        int tx = std::min(bx, 16), ty = std::min(by, 16);
+        int tz = std::min({bz, 16, std::max(1, 1024 / (tx * ty))});
+        for (;;) {
+            const long long S = (long long)sb(tx) * sb(ty) * sb(tz);
+            const long long Xs = (long long)sb(tz) * sb(ty) * tx, Ys = (long long)sb(tz) * ty * tx;
+            if (std::max(S, Ys) <= XA && Xs <= XB)
+                break;
+            if (tz > 1)
+                --tz;
+            else if (ty > 1)
+                --ty;
+            else
+                --tx;
+        }
+        for (int z = R.lo[2]; z < R.hi[2]; z += tz)
+            for (int y = R.lo[1]; y < R.hi[1]; y += ty)
+                for (int x = R.lo[0]; x < R.hi[0]; x += tx) {
+                    XTile T{};
+                    T.t = (int)t;
+                    const int lo[3] = {x, y, z}, tn[3] = {tx, ty, tz};
+                    for (int d = 0; d < 3; ++d) {
+                        T.lo[d] = lo[d];
+                        T.n[d] = std::min(tn[d], R.hi[d] - lo[d]);
+                        footprint(T.lo[d], T.n[d], R.c0[d], order, T.s0[d], T.sn[d]);
+                        T.dir[d] = d;
+                    }
+                    // the most shrinking direction first keeps the
+                    // intermediate results small
+                    std::stable_sort(T.dir, T.dir + 3, [&T](int p, int q) {
+                        return (long long)T.n[p] * T.sn[q] < (long long)T.n[q] * T.sn[p];
+                    });
+                    long long a, b;
+                    tile_lds(T, a, b);
+                    if (std::max(a, b) > XA) {   // fall back to x, y, z (fits by the bound)
+                        for (int d = 0; d < 3; ++d)
+                            T.dir[d] = d;
+                    }
+                    out.push_back(T);
+                }
+    }
+    return out;
+}
+
 int grid_for(long long total)
 {
     const long long g = (total + 255) / 256;
@@ -264,9 +462,28 @@ z4c_status z4c_xplan_create(const z4c_plan *plan, const z4c_transfer *prolong, i
         delete X;
         return st;
     }
-    const std::vector<long long> ps = prefix(X->pro), rs = prefix(X->res);
-    X->pro_total = ps.back();
+    const std::vector<long long> rs = prefix(X->res);
     X->res_total = rs.back();
+    X->tiles = make_tiles(X->pro, order);
+    for (const XTile &T : X->tiles) {
+        long long a, b;
+        tile_lds(T, a, b);
+        X->lds_a = std::max<long long>(X->lds_a, a);
+        X->lds_b = std::max<long long>(X->lds_b, b);
+        bool small = T.n[0] * T.n[1] * T.n[2] <= 1024;   // the kernel's index arithmetic
+        bool perm = T.dir[0] + T.dir[1] + T.dir[2] == 3 && T.dir[0] != T.dir[1]
+                 && T.dir[1] != T.dir[2] && T.dir[0] != T.dir[2];
+        for (int d = 0; d < 3; ++d)
+            small = small && T.n[d] <= 16 && T.sn[d] <= 16 && T.dir[d] >= 0 && T.dir[d] < 3;
+        if (a > XA || b > XB || !small || !perm) {   // the bound of make_tiles failed
+            delete X;
+            return set_error(Z4C_ENOTSUP, "prolongation tile exceeds its LDS");
+        }
+    }
+    if (X->tiles.size() > (size_t)INT32_MAX) {
+        delete X;
+        return set_error(Z4C_ENOTSUP, "too many prolongation tiles");
+    }
     if (!(flags & Z4C_PLAN_NO_DEVICE)) {
         if (!plan_blocks_device(plan)) {
             delete X;
@@ -281,7 +498,7 @@ z4c_status z4c_xplan_create(const z4c_plan *plan, const z4c_transfer *prolong, i
         };
         up((void **)&X->pro_d, X->pro.data(), sizeof(z4c_transfer) * X->pro.size());
         up((void **)&X->res_d, X->res.data(), sizeof(z4c_transfer) * X->res.size());
-        up((void **)&X->pro_start_d, ps.data(), sizeof(long long) * ps.size());
+        up((void **)&X->tiles_d, X->tiles.data(), sizeof(XTile) * X->tiles.size());
         up((void **)&X->res_start_d, rs.data(), sizeof(long long) * rs.size());
         if (e != hipSuccess) {
             z4c_xplan_destroy(X);
@@ -298,7 +515,7 @@ z4c_status z4c_xplan_destroy(z4c_xplan *X)
 {
     if (!X)
         return Z4C_OK;
-    for (void *p : {(void *)X->pro_d, (void *)X->res_d, (void *)X->pro_start_d,
+    for (void *p : {(void *)X->pro_d, (void *)X->res_d, (void *)X->tiles_d,
                     (void *)X->res_start_d})
         if (p)
             (void)hipFree(p);
@@ -316,20 +533,26 @@ static z4c_status xcall(const z4c_xplan *X, double *u, bool pro, hipStream_t s)
         return set_error(Z4C_EALIGN, "arrays must be 8-byte aligned");
     if (!X->device)
         return set_error(Z4C_ENODEV, "xplan was created without a device");
-    const long long total = pro ? X->pro_total : X->res_total;
-    if (total == 0)
-        return Z4C_OK;
     const z4c_block *blocks = plan_blocks_device(X->plan);
-    const int n = (int)(pro ? X->pro.size() : X->res.size());
-    const int g = grid_for(total);
-    if (!pro)
-        restrict_kernel<<<g, 256, 0, s>>>(blocks, X->res_d, X->res_start_d, n, total, u);
-    else if (X->order == 2)
-        prolong_kernel<2><<<g, 256, 0, s>>>(blocks, X->pro_d, X->pro_start_d, n, total, u);
-    else if (X->order == 4)
-        prolong_kernel<4><<<g, 256, 0, s>>>(blocks, X->pro_d, X->pro_start_d, n, total, u);
-    else
-        prolong_kernel<6><<<g, 256, 0, s>>>(blocks, X->pro_d, X->pro_start_d, n, total, u);
+    if (pro) {
+        const unsigned nt = (unsigned)X->tiles.size();
+        if (nt == 0)
+            return Z4C_OK;
+        const dim3 grid(nt, NFIELD);
+        const int a = (int)X->lds_a;
+        const size_t bytes = sizeof(double) * (size_t)(X->lds_a + X->lds_b);
+        if (X->order == 2)
+            prolong_kernel<2><<<grid, 256, bytes, s>>>(blocks, X->pro_d, X->tiles_d, a, u);
+        else if (X->order == 4)
+            prolong_kernel<4><<<grid, 256, bytes, s>>>(blocks, X->pro_d, X->tiles_d, a, u);
+        else
+            prolong_kernel<6><<<grid, 256, bytes, s>>>(blocks, X->pro_d, X->tiles_d, a, u);
+    } else {
+        if (X->res_total == 0)
+            return Z4C_OK;
+        restrict_kernel<<<grid_for(X->res_total), 256, 0, s>>>(blocks, X->res_d, X->res_start_d,
+                                             (int)X->res.size(), X->res_total, u);
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? Z4C_OK : set_hip_error(e, "intergrid kernel launch");
 }
