@@ -171,6 +171,7 @@ def main():
             for s in range(nstages):
                 stage_ms[s] += evs[2 * s].elapsed_time(evs[2 * s + 1])
         stage_ms /= reps
+        mon = monitor_timing(plan, regs, bt, stream, reps) if label == "fp64" else None
         # a stored-ghost refresh, timed alone for reference (not part of the step)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -180,7 +181,7 @@ def main():
         ghost_ms = e0.elapsed_time(e1)
         nonfinite = plan.check_finite(regs[0], stream=stream)
         results[label] = dict(ms=ms, stage_ms=stage_ms, ghost_ms=ghost_ms, launches=launches,
-                              nonfinite=nonfinite)
+                              nonfinite=nonfinite, monitor=mon)
         log(f"[bench] {label}: stage kernels {np.round(stage_ms, 3).tolist()} ms, "
             f"(a separate ghost refresh would cost {ghost_ms:.3f} ms), non-finite values "
             f"{nonfinite}")
@@ -239,6 +240,7 @@ def main():
         "zone_cycles_per_s": n_int / (r64["ms"] * 1e-3),
         "stage_kernel_ms": r64["stage_ms"].round(4).tolist(),
         "separate_ghost_refresh_ms": round(r64["ghost_ms"], 4),
+        "constraint_monitor": r64["monitor"],
         "roofline": {
             "bound": "hbm",
             "achieved": achieved_gbs,
@@ -269,6 +271,46 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
+
+
+def monitor_timing(plan, regs, bt, stream, reps):
+    """RK4 stage 2 of the level set in the tuned shapes: plain, with the
+    constraint monitor fused (constraint fields + per-block norms), and the
+    separate constraint pass it replaces; medians over `reps`."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import z4c as Z
+
+    nb = len(bt.blocks)
+    cons = torch.zeros(bt.total_c, dtype=torch.float64, device="cuda:0")
+    norms = torch.zeros(16 * nb, dtype=torch.float64, device="cuda:0")
+    calls = {
+        "stage_ms": lambda: plan.rk_stage(regs[1], regs[2], regs[3], regs[0], None, Z.RK4[1],
+                                          bt.dt, stream=stream),
+        "stage_with_monitor_ms": lambda: plan.rk_stage_monitor(
+            regs[1], regs[2], regs[3], regs[0], None, Z.RK4[1], bt.dt, cons, norms,
+            stream=stream),
+        "separate_constraints_ms": lambda: plan.constraints(regs[1], None, cons, norms,
+                                                            stream=stream),
+    }
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        out[name] = float(np.median(ms))
+    out["monitor_cost_ms"] = out["stage_with_monitor_ms"] - out["stage_ms"]
+    out["monitor_cost_vs_separate_pass"] = out["monitor_cost_ms"] / out["separate_constraints_ms"]
+    log(f"[bench] constraint monitor: {out}")
+    return out
 
 
 def profile_run(launches, stream):

@@ -189,6 +189,18 @@ z4c_status z4c_rk_stage(z4c_plan *plan, const double *u0_in, double *u0_out, dou
 z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter,
                            double *cons, double *norms, void *stream);
 
+/* z4c_rk_stage with the constraint monitor fused into the stage kernel (Sec.
+ * 4.1 monitoring): the stage as z4c_rk_stage, and the constraints of its
+ * input u0_in (the quantities and layouts of z4c_constraints) formed from
+ * the derivatives the stage takes anyway, so that monitoring adds no pass
+ * over the state.  `cons` (device, constraint layout) may be NULL; `norms`
+ * (device, nblocks*16 doubles, as z4c_constraints) must not.  Neither may
+ * alias a state or matter array.  FP64-arithmetic plans only (Z4C_ENOTSUP
+ * otherwise).  Values equal those of z4c_constraints up to rounding. */
+z4c_status z4c_rk_stage_monitor(z4c_plan *plan, const double *u0_in, double *u0_out, double *u1,
+                                const double *u2, const double *matter, const z4c_rk_coeffs *c,
+                                double dt, double *cons, double *norms, void *stream);
+
 /* Refresh the ghost points of `u` (device): periodic, neighbour (table set
  * with z4c_plan_set_neighbours; -1 entries take `frozen`, or keep their
  * stored value when `frozen` is NULL), or frozen (`frozen` device array in

@@ -379,9 +379,14 @@ z4c_status validate_stage(const z4c_plan *P, const double *u0_in, const double *
 
 z4c_status enqueue_stage(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
                          const double *u2, const double *matter, const z4c_rk_coeffs *c,
-                         double dt, hipStream_t s, int halo = -1, const double *frozen = nullptr)
+                         double dt, hipStream_t s, int halo = -1, const double *frozen = nullptr,
+                         bool monitor = false, double *cons = nullptr)
 {
     StageArgs a = base_args(P);
+    if (monitor) {
+        a.cons = cons;
+        a.partial = P->partial_d;
+    }
     if (halo >= 0) {
         a.halo = halo;
         a.frozen = frozen;
@@ -403,7 +408,7 @@ z4c_status enqueue_stage(z4c_plan *P, const double *u0_in, double *u0_out, doubl
     a.u2_is_u0 = u2 == u0_in;
     if (!a.use_u2)
         a.u2 = nullptr;
-    return run_groups(P, MODE_RK, P->params.arith, a, s);
+    return run_groups(P, monitor ? MODE_RK_MON : MODE_RK, P->params.arith, a, s);
 }
 
 z4c_status enqueue_ghost(z4c_plan *P, int policy, double *u, const double *frozen, hipStream_t s)
@@ -838,6 +843,38 @@ z4c_status z4c_rk_stage(z4c_plan *P, const double *u0_in, double *u0_out, double
     if (st != Z4C_OK)
         return st;
     return enqueue_stage(P, u0_in, u0_out, u1, u2, matter, c, dt, (hipStream_t)stream);
+}
+
+z4c_status z4c_rk_stage_monitor(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
+                                const double *u2, const double *matter, const z4c_rk_coeffs *c,
+                                double dt, double *cons, double *norms, void *stream)
+{
+    z4c_status st = validate_stage(P, u0_in, u0_out, u1, u2, matter, c, dt);
+    if (st != Z4C_OK)
+        return st;
+    if (!norms)
+        return fail(Z4C_EINVAL, "norms must not be NULL");
+    for (const double *x : {u0_in, (const double *)u0_out, (const double *)u1, u2, matter})
+        if (x && (x == cons || x == norms))
+            return fail(Z4C_EINVAL, "cons and norms must not alias a state or matter array");
+    if (cons && cons == norms)
+        return fail(Z4C_EINVAL, "cons must not alias norms");
+    if (!aligned8(cons) || !aligned8(norms))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (P->params.arith != Z4C_ARITH_FP64)
+        return fail(Z4C_ENOTSUP, "the constraint monitor runs with FP64 arithmetic only");
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = enqueue_stage(P, u0_in, u0_out, u1, u2, matter, c, dt, s, -1, nullptr, true, cons);
+    if (st != Z4C_OK)
+        return st;
+    const hipError_t e = launch_norm_reduce(P->blocks_d, P->nblocks, P->tile_start_d,
+                                            P->tile_count_d, P->partial_d, norms, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "norm reduction launch");
+    return Z4C_OK;
 }
 
 z4c_status z4c_constraints(z4c_plan *P, const double *u, const double *matter, double *cons,

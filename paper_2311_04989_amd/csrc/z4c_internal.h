@@ -21,7 +21,7 @@ enum MatterField : int { M_RHO = 0, M_SX, M_SY, M_SZ, M_SXX, M_SXY, M_SXZ, M_SYY
 enum ConsField : int { C_H = 0, C_MX, C_MY, C_MZ, C_THETA, C_ZX, C_ZY, C_ZZ, NCONS = 8 };
 
 // What a tile kernel produces.
-enum Mode : int { MODE_RHS = 0, MODE_RK = 1, MODE_CONS = 2 };
+enum Mode : int { MODE_RHS = 0, MODE_RK = 1, MODE_CONS = 2, MODE_RK_MON = 3 };
 
 // One work item of a tile kernel: block index and interior origin of the tile.
 struct Tile {
@@ -42,6 +42,7 @@ struct StageArgs {
     double *u1;
     const double *u2;
     double *partial;         // CONS: per-tile sums, [tile][16]
+    double *cons;            // RK_MON: constraint fields of the input (may be nullptr)
     // Runge-Kutta stage
     double delta, eps_dt, g1, g2, g3, beta_dt;
     int read_u1, write_u1, use_u2, u2_is_u0;
@@ -85,6 +86,9 @@ hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArg
                          hipStream_t s);
 hipError_t launch_p4(int mode, int arith, int tx, int ty, int tz, int w, const StageArgs &a,
                      hipStream_t s);
+// Stage with the constraint monitor (FP64, z4c_variants_mon.hip).
+hipError_t launch_monitor(int fd_order, int tx, int ty, int tz, int w, const StageArgs &a,
+                          hipStream_t s);
 hipError_t launch_ghost(const GhostArgs &g, long long total_ghost, hipStream_t s);
 hipError_t launch_norm_reduce(const z4c_block *blocks, int nblocks, const long long *tile_start,
                               const int *tile_count, const double *partial, double *norms,

@@ -157,6 +157,8 @@ bool stage_shape_supported(int fd_order, int tx, int ty, int tz, int waves)
 hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int tz, int waves,
                         const StageArgs &a, hipStream_t s)
 {
+    if (mode == MODE_RK_MON)
+        return launch_monitor(fd_order, tx, ty, tz, waves, a, s);
     if (fd_order == 4)
         return launch_p4(mode, arith, tx, ty, tz, waves, a, s);
     if (mode == MODE_CONS || arith != Z4C_ARITH_FP32)

@@ -1098,7 +1098,11 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
 // field's right-hand side is finished as soon as its last contribution is
 // known and, in a stage, combined with u1/u2 and stored at once; only the new
 // conformal metric and At are held back for the det/trace enforcement.
-template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN>
+// MON: the constraint monitor of the stage's input state (Sec. 4.1): H,
+// M_i, Theta and Z^i formed from the derivatives the stage takes anyway,
+// written to a.cons (when not null) and summed per tile into a.partial as
+// the constraint kernel does (same per-tile order).
+template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN, bool MON = false>
 __global__ void __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 stage_kernel(const StageArgs a)
 {
@@ -1125,9 +1129,12 @@ stage_kernel(const StageArgs a)
     // consecutive threads adjacent.
     constexpr int WG_PER_CU = (4 * WPE * 64 + NT - 1) / NT;
     __shared__ unsigned src_lds[NLD * NT];
+    // monitor: per-wave sums of |c| and c^2 of the 8 constraints
+    __shared__ double mred[MON ? (NT / 64) * 16 : 1];
     constexpr int SLOT_BUDGET =
         (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4
-         - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)) / (NT * (int)sizeof(R));
+         - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)
+         - (MON ? (NT / 64) * 16 * (int)sizeof(double) : 0)) / (NT * (int)sizeof(R));
     constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
     constexpr bool DB_SLOT = SLOT_BUDGET >= (GU_SLOT ? 27 : 9);
     constexpr int GU0 = 0, DB0 = GU_SLOT ? 18 : 0;
@@ -1301,6 +1308,27 @@ stage_kernel(const StageArgs a)
         auto adv = [&](const R d[3]) __attribute__((always_inline)) {
             return beta[0] * d[0] + beta[1] * d[1] + beta[2] * d[2];
         };
+        // Monitor: constraint q at this point (0 where inactive) to a.cons,
+        // and its |c|, c^2 summed over the wave (butterfly) into mred.
+        // Called by every lane of the workgroup.
+        double *cb = MON && a.cons ? a.cons + B.coffset : nullptr;
+        R Mc[3] = {R(0), R(0), R(0)};   // M_i accumulated over the stages
+        auto mon = [&](auto QC, R c_r) __attribute__((always_inline)) {
+            constexpr int q = decltype(QC)::value;
+            const double c = active ? double(c_r) : 0.0;
+            if (active && cb)
+                at(cb + q * fs, upt8) = c;
+            double v1 = fabs(c), v2 = c * c;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                v1 += __shfl_xor(v1, off, 64);
+                v2 += __shfl_xor(v2, off, 64);
+            }
+            if ((t & 63) == 0) {
+                mred[(t >> 6) * 16 + 2 * q] = v1;
+                mred[(t >> 6) * 16 + 2 * q + 1] = v2;
+            }
+        };
 
         // ---- shift: d beta (kept for the Lie-derivative terms), d d beta -> Gt
         R rG[3] = {R(0), R(0), R(0)};
@@ -1457,6 +1485,7 @@ stage_kernel(const StageArgs a)
         sfor<3>([&](auto K_c) __attribute__((always_inline)) {
             constexpr int kk = decltype(K_c)::value;
             stage(std::integral_constant<int, GAMX + kk>{});
+            R Zk = R(0);
             if (active) {
                 R d[3], ko;
                 first_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, ko);
@@ -1468,7 +1497,11 @@ stage_kernel(const StageArgs a)
                 const R Gam = R(lds[loff]);
                 rG[kk] += adv(d) + ko
                         - R(2) * alpha * kap1 * (Gam - Gd[kk]);
+                if constexpr (MON)
+                    Zk = R(0.5) * (Gam - Gd[kk]);
             }
+            if constexpr (MON)
+                mon(std::integral_constant<int, C_ZX + kk>{}, Zk);
         });
 
         // ---- chi: R^chi_ij; chi is complete.  With the Ricci tensor and At
@@ -1478,6 +1511,7 @@ stage_kernel(const StageArgs a)
         R dchi[3];
         R PA[6];                      // At source without the D_i D_j alpha term
         R Kpart = R(0), Tpart = R(0); // pointwise sources of Khat (without D^2 alpha), Theta
+        R Hc = R(0);                  // monitor: Hamiltonian constraint
         const Old oe_chi = stage(std::integral_constant<int, CHI>{});
         if (active) {
             const Old o = EARLY_OLD && early_old(CHI) ? oe_chi : old(CHI);
@@ -1566,6 +1600,23 @@ stage_kernel(const StageArgs a)
                   + alpha * kap1 * (R(1) - kap2) * Theta;
             Tpart = R(0.5) * alpha * (Rs - AA + R(2.0 / 3.0) * K * K)
                   - alpha * (R(8) * pi * rho + kap1 * (R(2) + kap2) * Theta);
+            if constexpr (MON) {
+                Hc = Rs + R(2.0 / 3.0) * K * K - AA - R(16) * pi * rho;
+                // M_i: -Gt_d^l At_li - Gt^l_ji At^j_l - 3/(2 chi) At^j_i d_j chi
+                // - 8 pi S_i here; the At and K derivative terms in their stages
+                sfor<3>([&](auto I_c) __attribute__((always_inline)) {
+                    constexpr int ii = decltype(I_c)::value;
+                    R m = -(Gd[0] * A[S(0, ii)] + Gd[1] * A[S(1, ii)] + Gd[2] * A[S(2, ii)]);
+                    sfor<3>([&](auto J_c) __attribute__((always_inline)) {
+                        constexpr int jj = decltype(J_c)::value;
+                        m -= GU(0, S(jj, ii)) * Amix[jj][0] + GU(1, S(jj, ii)) * Amix[jj][1]
+                           + GU(2, S(jj, ii)) * Amix[jj][2];
+                    });
+                    m -= R(1.5) / chis * (Amix[0][ii] * dchi[0] + Amix[1][ii] * dchi[1]
+                                          + Amix[2][ii] * dchi[2]);
+                    Mc[ii] += m - R(8) * pi * Si[ii];
+                });
+            }
             // At: chi [alpha (R - 8 pi S)]^tf + alpha (K At - 2 At At) + Lie
             // (the -chi [D D alpha]^tf part follows in the lapse stage)
             R Y[6];
@@ -1587,6 +1638,11 @@ stage_kernel(const StageArgs a)
                 PA[q] = chi * (Y[q] - g[q] * trY * R(1.0 / 3.0)) + alpha * (K * A[q] - R(2) * AAm)
                       + la - R(2.0 / 3.0) * A[q] * divb;
             });
+        }
+
+        if constexpr (MON) {
+            mon(std::integral_constant<int, C_H>{}, Hc);
+            mon(std::integral_constant<int, C_THETA>{}, Theta);
         }
 
         // ---- lapse: D_i D_j alpha; alpha is complete; the lapse terms of
@@ -1661,6 +1717,12 @@ stage_kernel(const StageArgs a)
                     constexpr int ii = decltype(I_c)::value;
                     rG[ii] += c * (gi[S(ii, 0)] * d[0] + gi[S(ii, 1)] * d[1] + gi[S(ii, 2)] * d[2]);
                 });
+                if constexpr (MON) {   // -2/3 d_i K, K = Khat + 2 Theta
+                    sfor<3>([&](auto I_c) __attribute__((always_inline)) {
+                        constexpr int ii = decltype(I_c)::value;
+                        Mc[ii] -= R(q == 0 ? 2.0 / 3.0 : 4.0 / 3.0) * d[ii];
+                    });
+                }
                 const R kq = adv(d) + ko + (q == 0 ? Kpart : Tpart);
                 finish(q == 0 ? KHAT : THETA, kq, staged(), o);
             }
@@ -1691,6 +1753,12 @@ stage_kernel(const StageArgs a)
                 }
                 R d[3], ko;
                 first_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, ko);
+                if constexpr (MON) {   // gt^{jk} d_k At_ij, At_ij = At_ji
+                    constexpr int ii = SI(q), jj = SJ(q);
+                    Mc[ii] += gi[S(jj, 0)] * d[0] + gi[S(jj, 1)] * d[1] + gi[S(jj, 2)] * d[2];
+                    if constexpr (ii != jj)
+                        Mc[jj] += gi[S(ii, 0)] * d[0] + gi[S(ii, 1)] * d[1] + gi[S(ii, 2)] * d[2];
+                }
                 const R kA = adv(d) + ko + PA[q];
                 if constexpr (RK)
                     vA[q] = combine(AXX + q, kA, staged(), o);
@@ -1716,6 +1784,20 @@ stage_kernel(const StageArgs a)
                     constexpr int q = decltype(Q_c)::value;
                     at(ob + (AXX + q) * fs, upt8) = vA[q] - vn[q] * tr * (1.0 / 3.0);
                 });
+            }
+        }
+        if constexpr (MON) {
+            sfor<3>([&](auto I_c) __attribute__((always_inline)) {
+                constexpr int ii = decltype(I_c)::value;
+                mon(std::integral_constant<int, C_MX + ii>{}, Mc[ii]);
+            });
+            __syncthreads();
+            // per-tile sums, the waves in order (as the constraint kernel)
+            if (t < 16) {
+                double sum = 0.0;
+                for (int w = 0; w < NT / 64; ++w)
+                    sum += mred[w * 16 + t];
+                a.partial[(a.tile_base + tile) * 16 + t] = sum;
             }
         }
         __syncthreads();   // LDS reuse by the next tile of a persistent workgroup
@@ -1751,6 +1833,22 @@ hipError_t launch_variant(int mode, const StageArgs &a, hipStream_t s)
         else
             tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, false><<<grid, blk, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+// Stage with the constraint monitor (FP64 arithmetic).
+template <int P, int TX, int TY, int TZ, int WPE>
+hipError_t launch_variant_mon(const StageArgs &a, hipStream_t s)
+{
+    const int grid = grid_size(a);
+    if (grid <= 0)
+        return hipSuccess;
+    const dim3 blk(TX * TY * TZ);
+    const bool gen = a.halo == Z4C_GHOST_FROZEN || a.halo == Z4C_GHOST_NEIGHBOUR;
+    if (gen)
+        tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RK, true, true><<<grid, blk, 0, s>>>(a);
+    else
+        tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RK, false, true><<<grid, blk, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -132,6 +132,8 @@ def lib():
         L.z4c_rk_stage.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
                                    ctypes.c_double, vp]
         L.z4c_constraints.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.z4c_rk_stage_monitor.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
+                                           ctypes.c_double, vp, vp, vp]
         L.z4c_ghost_fill.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.z4c_step.argtypes = [vp, ctypes.POINTER(StepDesc), ctypes.POINTER(ctypes.c_int), vp]
         L.z4c_step_graph.argtypes = [vp, ctypes.POINTER(StepDesc), ctypes.POINTER(ctypes.c_int),
@@ -164,7 +166,7 @@ def lib():
             getattr(L, name).restype = st
         for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params", "z4c_plan_set_halo",
                      "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
-                     "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill",
+                     "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill", "z4c_rk_stage_monitor",
                      "z4c_step", "z4c_step_graph", "z4c_plan_autotune", "z4c_check_finite"):
             getattr(L, name).restype = st
         _lib = L
@@ -269,6 +271,15 @@ class Plan:
         c = _coeffs(coeffs)
         _check(lib().z4c_rk_stage(self._h, _ptr(u0_in), _ptr(u0_out), _ptr(u1), _ptr(u2),
                                   _ptr(matter), ctypes.byref(c), float(dt), _stream(stream)))
+
+    def rk_stage_monitor(self, u0_in, u0_out, u1, u2, matter, coeffs, dt, cons, norms,
+                         stream=None):
+        """rk_stage plus the constraints of u0_in (cons may be None; norms as
+        in constraints), formed inside the stage kernel."""
+        c = _coeffs(coeffs)
+        _check(lib().z4c_rk_stage_monitor(self._h, _ptr(u0_in), _ptr(u0_out), _ptr(u1),
+                                          _ptr(u2), _ptr(matter), ctypes.byref(c), float(dt),
+                                          _ptr(cons), _ptr(norms), _stream(stream)))
 
     def constraints(self, u, matter, cons, norms, stream=None):
         _check(lib().z4c_constraints(self._h, _ptr(u), _ptr(matter), _ptr(cons), _ptr(norms),

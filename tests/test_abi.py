@@ -313,3 +313,35 @@ def test_intergrid_transfer_validation():
     assert e.value.status == Z.ENODEV
     xp.close()
     plan.close()
+
+
+def test_stage_monitor_validation():
+    """z4c_rk_stage_monitor: the stage's checks, then norms required, no
+    aliasing of the outputs with state or matter arrays, FP64 plans only;
+    valid arguments reach the device check."""
+    bt = W.Batch([W.Block(8, 6, 7, 3, 0.1, 0.1, 0.1)])
+    bt.params = W.Params(fd_order=4)
+    p = _plan(bt)
+    c = Z.RK4[1]
+    A, B, C, D, E, F, M = 0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000, 0x70000
+    cases = [
+        ((A, A, C, D, None, c, 0.1, E, F), Z.EINVAL),      # stage aliasing
+        ((A, B, C, D, None, c, 0.1, E, None), Z.EINVAL),   # norms required
+        ((A, B, C, D, None, c, 0.1, A, F), Z.EINVAL),      # cons aliases u0_in
+        ((A, B, C, D, None, c, 0.1, E, C), Z.EINVAL),      # norms aliases u1
+        ((A, B, C, D, M, c, 0.1, M, F), Z.EINVAL),         # cons aliases matter
+        ((A, B, C, D, None, c, 0.1, E, E), Z.EINVAL),      # cons aliases norms
+        ((A, B, C, D, None, c, 0.1, E + 4, F), Z.EALIGN),
+        ((A, B, C, D, None, c, 0.1, E, F), Z.ENODEV),
+        ((A, B, C, D, None, c, 0.1, None, F), Z.ENODEV),   # cons may be NULL
+    ]
+    for args, status in cases:
+        with pytest.raises(Z.Z4cError) as e:
+            p.rk_stage_monitor(*args)
+        assert e.value.status == status, (args, e.value)
+    p.close()
+    q = _plan(bt, arith=Z.ARITH_FP32)
+    with pytest.raises(Z.Z4cError) as e:
+        q.rk_stage_monitor(A, B, C, D, None, c, 0.1, E, F)
+    assert e.value.status == Z.ENOTSUP
+    q.close()
