@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-matter", action="store_true",
                     help="skip the matter-coupling kernels (metric to cells, ADM sources, "
                          "sources to vertices)")
+    ap.add_argument("--no-lopsided", action="store_true",
+                    help="skip the lopsided-advection stage timing")
     ap.add_argument("--no-intergrid", action="store_true",
                     help="skip the transfers between refinement levels")
     ap.add_argument("--intergrid-only", action="store_true",
@@ -264,6 +266,9 @@ def main():
                        "stage_kernel_ms": r32["stage_ms"].round(4).tolist()}
     if not args.no_batching:
         out["batching"] = batching(stream, args.steps)
+    if not args.no_lopsided:
+        out["lopsided_advection"] = lopsided_timing(bt, stream, max(3, args.steps // 2),
+                                                    r64["stage_ms"][1])
     if not args.no_matter:
         out["matter_coupling"] = matter_coupling(stream, args.steps)
     if not args.no_intergrid:
@@ -271,6 +276,43 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
+
+
+def lopsided_timing(bt, stream, reps, centred_ms):
+    """RK4 stage 2 of the level set with lopsided advection stencils (its own
+    plan, autotuned), against the centred stage of the main run."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import z4c as Z
+
+    params = dataclasses.replace(bt.params, advection=Z.ADVECT_LOPSIDED)
+    plan = Z.Plan(Z.make_params(params), Z.make_blocks(bt.block_table()))
+    u0 = torch.from_numpy(bt.u).to("cuda:0")
+    plan.ghost_fill(Z.GHOST_PERIODIC, u0, stream=stream)
+    plan.set_halo(Z.GHOST_PERIODIC)
+    out, u1 = u0.clone(), torch.zeros_like(u0)
+    plan.autotune(u0, out, u1, None, reps=3, stream=stream)
+    fn = lambda: plan.rk_stage(u0, out, u1, u0, None, Z.RK4[1], bt.dt, stream=stream)  # noqa: E731
+    fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = float(np.median(ms))
+    res = {"stage_ms": med, "centred_stage_ms": centred_ms, "ratio": med / centred_ms,
+           "launch_shapes": {str(k): plan.get_launch(k, k, k) for k in (8, 16, 24, 32)},
+           "achieved_gbs": bt.ninterior * STAGE_BYTES[1] / (med * 1e-3) / 1e9}
+    plan.close()
+    log(f"[bench] lopsided advection: {res}")
+    return res
 
 
 def monitor_timing(plan, regs, bt, stream, reps):

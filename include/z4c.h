@@ -62,6 +62,7 @@ typedef enum {
 typedef enum { Z4C_LAPSE_1PLUSLOG = 0, Z4C_LAPSE_HARMONIC = 1, Z4C_LAPSE_FROZEN = 2 } z4c_lapse;
 typedef enum { Z4C_SHIFT_GAMMADRIVER = 0, Z4C_SHIFT_FROZEN = 1 } z4c_shift;
 typedef enum { Z4C_ARITH_FP64 = 0, Z4C_ARITH_FP32 = 1 } z4c_arith;
+typedef enum { Z4C_ADVECT_CENTRED = 0, Z4C_ADVECT_LOPSIDED = 1 } z4c_advection;
 typedef enum {
     Z4C_GHOST_NONE = 0,       /* leave ghost values as they are               */
     Z4C_GHOST_PERIODIC = 1,   /* each block periodic on itself                */
@@ -86,13 +87,24 @@ typedef enum {
  *   arith        FP64: all arithmetic in double.  FP32: stencil differences
  *                u_m - u_0 are formed in double, then the derivatives,
  *                dissipation and the pointwise algebra run in float; storage,
- *                the Runge-Kutta combination and the floors stay double. */
+ *                the Runge-Kutta combination and the floors stay double.
+ *   advection    stencil of the advection terms beta^k d_k u (every field):
+ *                CENTRED (the fd_order first derivative) or LOPSIDED, the
+ *                fd_order-accurate first derivative on the points shifted by
+ *                one towards the sign of beta^k (offsets -p/2+1 .. p/2+1
+ *                for beta^k > 0, mirrored otherwise; the paper gives no
+ *                advection stencil, this is the usual upwind-biased choice
+ *                of moving-puncture codes).  LOPSIDED needs FP64 arithmetic
+ *                (Z4C_ENOTSUP otherwise).  The field sits in the padding
+ *                after `arith`: the struct stays 80 bytes and a zeroed
+ *                struct means CENTRED. */
 typedef struct {
     int fd_order;
     double ko_sigma, kappa1, kappa2, eta;
     int lapse, shift, advect_gauge;
     double chi_floor, alpha_floor;
     int arith;
+    int advection;
 } z4c_params;
 
 /* One MeshBlock (72 bytes). dx, dy, dz > 0; nx, ny, nz >= 1. */
@@ -196,7 +208,9 @@ z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter
  * over the state.  `cons` (device, constraint layout) may be NULL; `norms`
  * (device, nblocks*16 doubles, as z4c_constraints) must not.  Neither may
  * alias a state or matter array.  FP64-arithmetic plans only (Z4C_ENOTSUP
- * otherwise).  Values equal those of z4c_constraints up to rounding. */
+ * otherwise), centred advection only (the monitor kernel has no lopsided
+ * form: Z4C_ENOTSUP).  Values equal those of z4c_constraints up to
+ * rounding. */
 z4c_status z4c_rk_stage_monitor(z4c_plan *plan, const double *u0_in, double *u0_out, double *u1,
                                 const double *u2, const double *matter, const z4c_rk_coeffs *c,
                                 double dt, double *cons, double *norms, void *stream);

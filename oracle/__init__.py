@@ -43,7 +43,7 @@ class _Params(ctypes.Structure):
                 ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double),
                 ("eta", ctypes.c_double), ("lapse", ctypes.c_int), ("shift", ctypes.c_int),
                 ("advect_gauge", ctypes.c_int), ("chi_floor", ctypes.c_double),
-                ("alpha_floor", ctypes.c_double)]
+                ("alpha_floor", ctypes.c_double), ("advection", ctypes.c_int)]
 
 
 class _RK(ctypes.Structure):
@@ -91,6 +91,7 @@ def lib(ext: bool = False):
                                      ctypes.POINTER(ctypes.c_int), dp, dp]
         L.orc_derivs.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, dp, dp]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_lopsided_weights.argtypes = [ctypes.c_int, dp]
         _libs[ext] = L
     return _libs[ext]
 
@@ -105,7 +106,17 @@ def _dp(a):
 def _params(p) -> _Params:
     return _Params(int(p.fd_order), float(p.ko_sigma), float(p.kappa1), float(p.kappa2),
                    float(p.eta), int(p.lapse), int(p.shift), int(p.advect_gauge),
-                   float(p.chi_floor), float(p.alpha_floor))
+                   float(p.chi_floor), float(p.alpha_floor),
+                   int(getattr(p, "advection", 0)))
+
+
+def lopsided_weights(p: int) -> np.ndarray:
+    """The oracle's lopsided first-derivative weights of order p (units 1/h)
+    at offsets -p/2+1 .. p/2+1 (the stencil for beta > 0)."""
+    w = np.zeros(p + 1)
+    if lib().orc_lopsided_weights(int(p), _dp(w)) != 0:
+        raise ValueError("order must be 4 or 6")
+    return w
 
 
 def max_threads() -> int:

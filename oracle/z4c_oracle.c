@@ -69,6 +69,7 @@ typedef struct {
     int shift;          /* 0: Gamma-driver, 1: frozen        */
     int advect_gauge;   /* 1: beta^k d_k on alpha and beta   */
     double chi_floor, alpha_floor;
+    int advection;      /* 0: centred, 1: lopsided advection stencils */
 } orc_params;
 
 typedef struct {
@@ -95,6 +96,83 @@ static real d1(const double *u, long s, real h, int p)
     if (p == 4)
         return (8 * (U(s) - U(-s)) - (U(2 * s) - U(-2 * s))) / (12 * h);
     return (45 * (U(s) - U(-s)) - 9 * (U(2 * s) - U(-2 * s)) + (U(3 * s) - U(-3 * s))) / (60 * h);
+}
+
+/* Lopsided first derivative, order p (the advection stencil of moving-
+ * puncture codes; the paper names no advection stencil): the first
+ * derivative on the p + 1 points shifted by one towards the sign of beta,
+ * offsets -p/2+1 .. p/2+1 for beta > 0 and the mirror image otherwise.  Its
+ * weights are, by definition, the unique ones exact on every polynomial of
+ * degree <= p: sum_j w_j j^m = [m == 1] (m = 0..p, j over the offsets),
+ * solved once per order by Gaussian elimination with partial pivoting.
+ * LOPW[q][j] holds the weights of order 4 (q = 0) and 6 (q = 1) for offset
+ * -p/2+1 + j. */
+static long double LOPW[2][7];
+
+static void lop_solve(int p, long double *w)
+{
+    const int n = p + 1, lo = -p / 2 + 1;
+    long double A[7][8];
+    for (int m = 0; m < n; ++m) {
+        for (int j = 0; j < n; ++j) {
+            long double x = 1.0L;
+            for (int e = 0; e < m; ++e)
+                x *= (long double)(lo + j);
+            A[m][j] = x;
+        }
+        A[m][n] = (m == 1) ? 1.0L : 0.0L;
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabsl(A[r][c]) > fabsl(A[piv][c]))
+                piv = r;
+        for (int e = 0; e <= n; ++e) {
+            const long double t = A[c][e];
+            A[c][e] = A[piv][e];
+            A[piv][e] = t;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c)
+                continue;
+            const long double f = A[r][c] / A[c][c];
+            for (int e = c; e <= n; ++e)
+                A[r][e] -= f * A[c][e];
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        w[j] = A[j][n] / A[j][j];
+}
+
+static void lop_init(void)
+{
+    lop_solve(4, LOPW[0]);
+    lop_solve(6, LOPW[1]);
+}
+
+/* Weights of order p for the offsets -p/2+1 .. p/2+1 (host array of p+1). */
+int orc_lopsided_weights(int p, double *w)
+{
+    if (p != 4 && p != 6)
+        return -1;
+    long double v[7];
+    lop_solve(p, v);
+    for (int j = 0; j <= p; ++j)
+        w[j] = (double)v[j];
+    return 0;
+}
+
+static real d1lop(const double *u, long s, real h, int p, int pos)
+{
+    const long double *w = LOPW[p == 6];
+    const int lo = -p / 2 + 1;
+    const real c = U(0);
+    real acc = 0.0;
+    for (int j = 0; j <= p; ++j) {
+        const long o = pos ? (long)(lo + j) : -(long)(lo + j);
+        acc += (real)w[j] * (U(o * s) - c);   /* the weights sum to zero */
+    }
+    return (pos ? acc : -acc) / h;
 }
 
 /* Second derivative, centred, order p: weights sum to zero, so it is written
@@ -190,6 +268,7 @@ typedef struct {
     real du[NFIELD][3];      /* d_k u_f                               */
     real ddu[NFIELD][3][3];  /* d_k d_l u_f (only for fields needing it) */
     real ko[NFIELD];         /* sum over directions of the KO operator */
+    real dl[NFIELD][3];      /* lopsided d_k u_f (advection = 1 only)  */
     real m[NMATTER];         /* matter at the point (0 if absent)     */
 } point_data;
 
@@ -228,6 +307,13 @@ static void gather(const orc_params *P, const orc_block *B, const double *u,
             for (int a = 0; a < 3; ++a)
                 q += ko1(c, s[a], h[a], p, P->ko_sigma);
             pd->ko[f] = q;
+        }
+    }
+    if (P->advection == 1) {
+        for (int f = 0; f < NFIELD; ++f) {
+            const double *c = u + B->offset + (long long)f * B->field_stride + pt;
+            for (int a = 0; a < 3; ++a)
+                pd->dl[f][a] = d1lop(c, s[a], h[a], p, pd->u[BETAX + a] > 0.0);
         }
     }
     if (matter) {
@@ -436,7 +522,7 @@ static void point_rhs(const orc_params *P, const point_data *pd, real rhs[NFIELD
     for (int f = 0; f < NFIELD; ++f) {
         real s = 0.0;
         for (int k = 0; k < 3; ++k)
-            s += beta[k] * pd->du[f][k];
+            s += beta[k] * (P->advection == 1 ? pd->dl[f][k] : pd->du[f][k]);
         adv[f] = s;
     }
 
@@ -642,6 +728,7 @@ int orc_rhs(const orc_params *P, const orc_block *blocks, int nb, const double *
     long nw;
     work_item *w = make_work(blocks, nb, &nw);
     set_threads(nthreads);
+    lop_init();
 #pragma omp parallel for schedule(dynamic, 1)
     for (long t = 0; t < nw; ++t) {
         const orc_block *B = &blocks[w[t].b];
@@ -670,6 +757,7 @@ int orc_rk_stage(const orc_params *P, const orc_block *blocks, int nb, const dou
     long nw;
     work_item *w = make_work(blocks, nb, &nw);
     set_threads(nthreads);
+    lop_init();
 #pragma omp parallel for schedule(dynamic, 1)
     for (long t = 0; t < nw; ++t) {
         const orc_block *B = &blocks[w[t].b];

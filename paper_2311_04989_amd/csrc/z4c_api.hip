@@ -89,6 +89,10 @@ z4c_status check_params(const z4c_params *p)
         return fail(Z4C_EINVAL, "chi_floor must be > 0 and alpha_floor >= 0");
     if (p->arith != Z4C_ARITH_FP64 && p->arith != Z4C_ARITH_FP32)
         return fail(Z4C_EINVAL, "arith must be FP64 or FP32");
+    if (p->advection != Z4C_ADVECT_CENTRED && p->advection != Z4C_ADVECT_LOPSIDED)
+        return fail(Z4C_EINVAL, "advection must be CENTRED or LOPSIDED");
+    if (p->advection == Z4C_ADVECT_LOPSIDED && p->arith != Z4C_ARITH_FP64)
+        return fail(Z4C_ENOTSUP, "lopsided advection runs with FP64 arithmetic only");
     return Z4C_OK;
 }
 
@@ -332,8 +336,12 @@ z4c_status run_groups(z4c_plan *P, int mode, int arith, StageArgs a, hipStream_t
         a.ntiles = (int)g.tiles.size();
         a.persistent = g.persistent;
         a.tile_base = g.tile_base;
-        const hipError_t e = launch_stage(mode, P->params.fd_order, arith, g.tx, g.ty, g.tz,
-                                          g.waves, a, s);
+        const bool lop = P->params.advection == Z4C_ADVECT_LOPSIDED
+                      && (mode == MODE_RHS || mode == MODE_RK);
+        const hipError_t e = lop ? launch_lopsided(mode, P->params.fd_order, g.tx, g.ty, g.tz,
+                                                   g.waves, a, s)
+                                 : launch_stage(mode, P->params.fd_order, arith, g.tx, g.ty,
+                                                g.tz, g.waves, a, s);
         if (e != hipSuccess)
             return hip_fail(e, "tile kernel launch");
     }
@@ -863,6 +871,8 @@ z4c_status z4c_rk_stage_monitor(z4c_plan *P, const double *u0_in, double *u0_out
         return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
     if (P->params.arith != Z4C_ARITH_FP64)
         return fail(Z4C_ENOTSUP, "the constraint monitor runs with FP64 arithmetic only");
+    if (P->params.advection != Z4C_ADVECT_CENTRED)
+        return fail(Z4C_ENOTSUP, "the constraint monitor has centred advection only");
     st = need_device(P);
     if (st != Z4C_OK)
         return st;

@@ -86,6 +86,9 @@ hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArg
                          hipStream_t s);
 hipError_t launch_p4(int mode, int arith, int tx, int ty, int tz, int w, const StageArgs &a,
                      hipStream_t s);
+// Right-hand side / stage with lopsided advection (FP64, z4c_variants_lop.hip).
+hipError_t launch_lopsided(int mode, int fd_order, int tx, int ty, int tz, int w,
+                           const StageArgs &a, hipStream_t s);
 // Stage with the constraint monitor (FP64, z4c_variants_mon.hip).
 hipError_t launch_monitor(int fd_order, int tx, int ty, int tz, int w, const StageArgs &a,
                           hipStream_t s);

@@ -161,6 +161,32 @@ __device__ __forceinline__ void axis3(const C &c, R f1, R f2, R fk, R &d1, R &d2
     }
 }
 
+// Lopsided first derivative along one axis, unscaled (same 1/(c1 h) factor
+// as the centred one): the order-P stencil on the points shifted by one
+// towards the side `pos` (offsets -P/2+1 .. P/2+1 when pos, mirrored
+// otherwise), in differences from the centre.  Weights, exact on
+// polynomials of degree <= P: order 6 (2, -24, -35, 80, -30, 8, -1) / 60 at
+// offsets -2 .. 4; order 4 (-3, -10, 18, -6, 1) / 12 at offsets -1 .. 3.
+template <int P, typename R, int ST, typename C>
+__device__ __forceinline__ R lop1(const C &c, bool pos)
+{
+    const double c0 = c[0];
+    double a[P / 2 + 2], b[P / 2 + 2];   // a: the shifted side, b: the other
+#pragma unroll
+    for (int q = 1; q <= P / 2 + 1; ++q) {
+        const double pq = c[q * ST], mq = c[-q * ST];
+        a[q] = pos ? pq : mq;
+        b[q] = pos ? mq : pq;
+    }
+    R v;
+    if constexpr (P == 4)
+        v = -R(3) * R(b[1] - c0) + R(18) * R(a[1] - c0) - R(6) * R(a[2] - c0) + R(a[3] - c0);
+    else
+        v = R(2) * R(b[2] - c0) - R(24) * R(b[1] - c0) + R(80) * R(a[1] - c0)
+            - R(30) * R(a[2] - c0) + R(8) * R(a[3] - c0) - R(a[4] - c0);
+    return pos ? v : -v;
+}
+
 // Stencil taps addressed from the lower corner of the halo box (CO elements
 // before the centre), so that every tap is a non-negative constant offset
 // from one base address.
@@ -305,6 +331,17 @@ __device__ __forceinline__ void all_ko_sums(const double *L, int off, const Fac<
     dd[1] = d1sum<P, R, TX>(px) * F.mix[0];
     dd[2] = d1sum<P, R, TX * M::DY>(px) * F.mix[1];
     dd[4] = d1sum<P, R, TX * TY>(py) * F.mix[2];
+}
+
+// beta^k d_k of the field staged in L with lopsided derivatives.
+template <int P, typename R, int PX, int PXY>
+__device__ __forceinline__ R lop_adv(const double *L, int off, const Fac<R> &F, const R beta[3])
+{
+    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
+    const Corner<CO> c{L + corner(off - CO)};
+    return beta[0] * (lop1<P, R, 1>(c, beta[0] > R(0)) * F.d1[0])
+         + beta[1] * (lop1<P, R, PX>(c, beta[1] > R(0)) * F.d1[1])
+         + beta[2] * (lop1<P, R, PXY>(c, beta[2] > R(0)) * F.d1[2]);
 }
 
 // Unfused helpers used by the constraint kernel.
@@ -1102,7 +1139,10 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
 // M_i, Theta and Z^i formed from the derivatives the stage takes anyway,
 // written to a.cons (when not null) and summed per tile into a.partial as
 // the constraint kernel does (same per-tile order).
-template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN, bool MON = false>
+// LOP: lopsided stencils in the advection terms beta^k d_k u (re-read from
+// the staged field in LDS); every other derivative stays centred.
+template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN, bool MON = false,
+          bool LOP = false>
 __global__ void __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 stage_kernel(const StageArgs a)
 {
@@ -1306,7 +1346,10 @@ stage_kernel(const StageArgs a)
         const R pi = R(PI);
 
         auto adv = [&](const R d[3]) __attribute__((always_inline)) {
-            return beta[0] * d[0] + beta[1] * d[1] + beta[2] * d[2];
+            if constexpr (LOP)
+                return lop_adv<P, R, PX, PXY>(lds, loff, F, beta);
+            else
+                return beta[0] * d[0] + beta[1] * d[1] + beta[2] * d[2];
         };
         // Monitor: constraint q at this point (0 where inactive) to a.cons,
         // and its |c|, c^2 summed over the wave (butterfly) into mred.
@@ -1832,6 +1875,33 @@ hipError_t launch_variant(int mode, const StageArgs &a, hipStream_t s)
             tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, true><<<grid, blk, 0, s>>>(a);
         else
             tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, false><<<grid, blk, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+// Right-hand side or stage with lopsided advection (FP64 arithmetic).
+template <int P, int TX, int TY, int TZ, int WPE>
+hipError_t launch_variant_lop(int mode, const StageArgs &a, hipStream_t s)
+{
+    const int grid = grid_size(a);
+    if (grid <= 0)
+        return hipSuccess;
+    const dim3 blk(TX * TY * TZ);
+    const bool gen = a.halo == Z4C_GHOST_FROZEN || a.halo == Z4C_GHOST_NEIGHBOUR;
+    if (mode == MODE_RHS) {
+        if (gen)
+            tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RHS, true, false, true>
+                <<<grid, blk, 0, s>>>(a);
+        else
+            tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RHS, false, false, true>
+                <<<grid, blk, 0, s>>>(a);
+    } else {
+        if (gen)
+            tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RK, true, false, true>
+                <<<grid, blk, 0, s>>>(a);
+        else
+            tile::stage_kernel<P, TX, TY, TZ, WPE, double, MODE_RK, false, false, true>
+                <<<grid, blk, 0, s>>>(a);
     }
     return hipGetLastError();
 }

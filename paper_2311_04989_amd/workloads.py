@@ -99,6 +99,7 @@ class Params:
     advect_gauge: int = 1
     chi_floor: float = 1e-6
     alpha_floor: float = 1e-8
+    advection: int = 0        # 0 centred, 1 lopsided (shifted towards the sign of beta^k)
 
 
 def _pad_even(n: int) -> int:

@@ -19,6 +19,7 @@ OK, EINVAL, ENOGHOST, EALIGN, EHIP, ENOTSUP, ENOMEM, ENODEV = 0, -1, -2, -3, -4,
 LAPSE_1PLUSLOG, LAPSE_HARMONIC, LAPSE_FROZEN = 0, 1, 2
 SHIFT_GAMMADRIVER, SHIFT_FROZEN = 0, 1
 ARITH_FP64, ARITH_FP32 = 0, 1
+ADVECT_CENTRED, ADVECT_LOPSIDED = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
 STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL = 1, 2
@@ -29,7 +30,8 @@ class Params(ctypes.Structure):
                 ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double),
                 ("eta", ctypes.c_double), ("lapse", ctypes.c_int), ("shift", ctypes.c_int),
                 ("advect_gauge", ctypes.c_int), ("chi_floor", ctypes.c_double),
-                ("alpha_floor", ctypes.c_double), ("arith", ctypes.c_int)]
+                ("alpha_floor", ctypes.c_double), ("arith", ctypes.c_int),
+                ("advection", ctypes.c_int)]
 
 
 class Block(ctypes.Structure):
@@ -182,7 +184,8 @@ def make_params(p, arith: int = ARITH_FP64) -> Params:
     """C parameters from any object with the scheme-parameter attributes."""
     return Params(int(p.fd_order), float(p.ko_sigma), float(p.kappa1), float(p.kappa2),
                   float(p.eta), int(p.lapse), int(p.shift), int(p.advect_gauge),
-                  float(p.chi_floor), float(p.alpha_floor), int(arith))
+                  float(p.chi_floor), float(p.alpha_floor), int(arith),
+                  int(getattr(p, "advection", ADVECT_CENTRED)))
 
 
 def make_blocks(table: np.ndarray):

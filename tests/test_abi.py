@@ -52,6 +52,7 @@ def test_structure_layouts_match_header_sizes():
     assert W.MBLOCK_DTYPE.itemsize == 96
     assert ctypes.sizeof(Z.C2PParams) == 72
     assert ctypes.sizeof(Z.Fluid) == 24
+    assert ctypes.sizeof(Z.Params) == 80   # advection sits in the padding after arith
 
 
 def test_matter_coupling_validation_before_device():
@@ -345,3 +346,25 @@ def test_stage_monitor_validation():
         q.rk_stage_monitor(A, B, C, D, None, c, 0.1, E, F)
     assert e.value.status == Z.ENOTSUP
     q.close()
+
+
+def test_advection_parameter_validation():
+    """advection: CENTRED or LOPSIDED; LOPSIDED with FP64 arithmetic only;
+    the stage monitor refuses a lopsided plan."""
+    bt = W.Batch([W.Block(8, 6, 7, 4, 0.1, 0.1, 0.1)])
+    bt.params = W.Params(fd_order=6)
+    with pytest.raises(Z.Z4cError) as e:
+        _plan(bt, advection=2)
+    assert e.value.status == Z.EINVAL
+    with pytest.raises(Z.Z4cError) as e:
+        _plan(bt, advection=Z.ADVECT_LOPSIDED, arith=Z.ARITH_FP32)
+    assert e.value.status == Z.ENOTSUP
+    p = _plan(bt, advection=Z.ADVECT_LOPSIDED)
+    A, B, C, D, E, F = 0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000
+    with pytest.raises(Z.Z4cError) as e:
+        p.rk_stage_monitor(A, B, C, D, None, Z.RK4[1], 0.1, E, F)
+    assert e.value.status == Z.ENOTSUP
+    with pytest.raises(Z.Z4cError) as e:
+        p.rk_stage(A, B, C, D, None, Z.RK4[1], 0.1)
+    assert e.value.status == Z.ENODEV
+    p.close()
