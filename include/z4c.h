@@ -237,6 +237,10 @@ z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *f
  * step can be repeated with the same registers). */
 #define Z4C_STEP_STORED_GHOSTS 1   /* refresh stored ghosts after every stage    */
 #define Z4C_STEP_NO_FINAL_FILL 2   /* do not refresh the final state's ghosts     */
+#define Z4C_STEP_MONITOR 4         /* stage 0 with the fused constraint monitor:
+                                      the constraints of y_n (regs[0] on entry) into
+                                      cons (may be NULL) and norms, as
+                                      z4c_rk_stage_monitor; no extra pass */
 typedef struct {
     double *regs[4];
     const double *matter;
@@ -246,7 +250,9 @@ typedef struct {
     int ghost_policy;
     const double *frozen;
     int flags;                    /* Z4C_STEP_* */
-} z4c_step_desc;
+    double *cons;                 /* Z4C_STEP_MONITOR: constraint fields or NULL  */
+    double *norms;                /* Z4C_STEP_MONITOR: nblocks*16 doubles         */
+} z4c_step_desc;                  /* 104 bytes */
 z4c_status z4c_step(z4c_plan *plan, const z4c_step_desc *desc, int *result, void *stream);
 
 /* Same as z4c_step, but the whole step (stages + ghost fills) is captured

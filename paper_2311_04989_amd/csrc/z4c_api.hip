@@ -57,6 +57,7 @@ struct StepKey {
     const double *frozen;
     double dt;
     int nstages, ghost_policy, flags;
+    double *cons, *norms;
     z4c_rk_coeffs table[8];
     int version;
     bool operator==(const StepKey &o) const { return std::memcmp(this, &o, sizeof(StepKey)) == 0; }
@@ -515,8 +516,26 @@ z4c_status validate_step(const z4c_plan *P, const z4c_step_desc *d)
         if ((c.read_u1 || c.write_u1 || c.g2 != 0.0) && !d->regs[3])
             return fail(Z4C_EINVAL, "regs[3] (accumulator) is NULL but a stage uses it");
     }
-    if (d->flags & ~(Z4C_STEP_STORED_GHOSTS | Z4C_STEP_NO_FINAL_FILL))
+    if (d->flags & ~(Z4C_STEP_STORED_GHOSTS | Z4C_STEP_NO_FINAL_FILL | Z4C_STEP_MONITOR))
         return fail(Z4C_EINVAL, "unknown step flags");
+    if (d->flags & Z4C_STEP_MONITOR) {
+        if (!d->norms)
+            return fail(Z4C_EINVAL, "Z4C_STEP_MONITOR needs norms");
+        if (d->cons && d->cons == d->norms)
+            return fail(Z4C_EINVAL, "cons must not alias norms");
+        for (const double *x : {(const double *)d->regs[0], (const double *)d->regs[1],
+                                (const double *)d->regs[2], (const double *)d->regs[3],
+                                d->matter, d->frozen})
+            if (x && (x == d->cons || x == d->norms))
+                return fail(Z4C_EINVAL, "cons and norms must not alias a register, matter or "
+                                        "frozen");
+        if (!aligned8(d->cons) || !aligned8(d->norms))
+            return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+        if (P && P->params.arith != Z4C_ARITH_FP64)
+            return fail(Z4C_ENOTSUP, "the constraint monitor runs with FP64 arithmetic only");
+        if (P && P->params.advection != Z4C_ADVECT_CENTRED)
+            return fail(Z4C_ENOTSUP, "the constraint monitor has centred advection only");
+    }
     return validate_ghost(P, d->ghost_policy, d->regs[0], d->frozen);
 }
 
@@ -532,14 +551,22 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
                         || !P->offsets32;
     for (int k = 0; k < d->nstages; ++k) {
         const double *y = d->regs[0];
+        const bool mon = k == 0 && (d->flags & Z4C_STEP_MONITOR);
         if (stored) {
             st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
-                               &d->table[k], d->dt, s, Z4C_GHOST_NONE, nullptr);
+                               &d->table[k], d->dt, s, Z4C_GHOST_NONE, nullptr, mon, d->cons);
             if (st == Z4C_OK)
                 st = enqueue_ghost(P, d->ghost_policy, d->regs[out[k]], d->frozen, s);
         } else {
             st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
-                               &d->table[k], d->dt, s, d->ghost_policy, d->frozen);
+                               &d->table[k], d->dt, s, d->ghost_policy, d->frozen, mon,
+                               d->cons);
+        }
+        if (st == Z4C_OK && mon) {
+            const hipError_t e = launch_norm_reduce(P->blocks_d, P->nblocks, P->tile_start_d,
+                                                    P->tile_count_d, P->partial_d, d->norms, s);
+            if (e != hipSuccess)
+                st = hip_fail(e, "norm reduction launch");
         }
         if (st != Z4C_OK)
             return st;
@@ -988,6 +1015,8 @@ z4c_status z4c_step_graph(z4c_plan *P, const z4c_step_desc *d, int *result, void
     key.nstages = d->nstages;
     key.ghost_policy = d->ghost_policy;
     key.flags = d->flags;
+    key.cons = d->cons;
+    key.norms = d->norms;
     for (int s = 0; s < d->nstages; ++s)
         key.table[s] = d->table[s];
     key.version = P->version;

@@ -22,7 +22,7 @@ ARITH_FP64, ARITH_FP32 = 0, 1
 ADVECT_CENTRED, ADVECT_LOPSIDED = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
-STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL = 1, 2
+STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL, STEP_MONITOR = 1, 2, 4
 
 
 class Params(ctypes.Structure):
@@ -57,7 +57,8 @@ class StepDesc(ctypes.Structure):
     _fields_ = [("regs", ctypes.c_void_p * 4), ("matter", ctypes.c_void_p),
                 ("table", ctypes.POINTER(RKCoeffs)), ("nstages", ctypes.c_int),
                 ("dt", ctypes.c_double), ("ghost_policy", ctypes.c_int),
-                ("frozen", ctypes.c_void_p), ("flags", ctypes.c_int)]
+                ("frozen", ctypes.c_void_p), ("flags", ctypes.c_int),
+                ("cons", ctypes.c_void_p), ("norms", ctypes.c_void_p)]
 
 
 # Classic RK4 in the library's three-register stage form.
@@ -292,7 +293,7 @@ class Plan:
         _check(lib().z4c_ghost_fill(self._h, int(policy), _ptr(u), _ptr(frozen),
                                     _stream(stream)))
 
-    def _desc(self, regs, matter, table, dt, ghost, frozen, flags=0):
+    def _desc(self, regs, matter, table, dt, ghost, frozen, flags=0, cons=None, norms=None):
         tab = (RKCoeffs * len(table))(*[_coeffs(c) for c in table])
         d = StepDesc()
         for r in range(4):
@@ -304,13 +305,16 @@ class Plan:
         d.ghost_policy = int(ghost)
         d.frozen = _ptr(frozen)
         d.flags = int(flags)
+        d.cons = _ptr(cons)
+        d.norms = _ptr(norms)
         return d, tab
 
     def step(self, regs, matter, table, dt, ghost, frozen=None, stream=None, graph=False,
-             flags=0) -> int:
+             flags=0, cons=None, norms=None) -> int:
         """One Runge-Kutta step; returns the index of the register holding the
-        new state."""
-        d, tab = self._desc(regs, matter, table, dt, ghost, frozen, flags)
+        new state.  With flags & STEP_MONITOR the constraints of the state on
+        entry go to cons (or None) and norms."""
+        d, tab = self._desc(regs, matter, table, dt, ghost, frozen, flags, cons, norms)
         res = ctypes.c_int(-1)
         fn = lib().z4c_step_graph if graph else lib().z4c_step
         _check(fn(self._h, ctypes.byref(d), ctypes.byref(res), _stream(stream)))

@@ -53,6 +53,7 @@ def test_structure_layouts_match_header_sizes():
     assert ctypes.sizeof(Z.C2PParams) == 72
     assert ctypes.sizeof(Z.Fluid) == 24
     assert ctypes.sizeof(Z.Params) == 80   # advection sits in the padding after arith
+    assert ctypes.sizeof(Z.StepDesc) == 104
 
 
 def test_matter_coupling_validation_before_device():
@@ -368,3 +369,28 @@ def test_advection_parameter_validation():
         p.rk_stage(A, B, C, D, None, Z.RK4[1], 0.1)
     assert e.value.status == Z.ENODEV
     p.close()
+
+
+def test_step_monitor_validation():
+    """Z4C_STEP_MONITOR: norms required, no aliasing with registers, FP64 and
+    centred advection only; valid arguments reach the device check."""
+    bt = W.Batch([W.Block(8, 6, 7, 4, 0.1, 0.1, 0.1)])
+    bt.params = W.Params(fd_order=6)
+    p = _plan(bt)
+    A, B, C, D, E, F = 0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000
+    regs = [A, B, C, D]
+    cases = [(dict(cons=E, norms=None), Z.EINVAL), (dict(cons=A, norms=F), Z.EINVAL),
+             (dict(cons=E, norms=D), Z.EINVAL), (dict(cons=E, norms=E), Z.EINVAL),
+             (dict(cons=E, norms=F + 4), Z.EALIGN), (dict(cons=None, norms=F), Z.ENODEV),
+             (dict(cons=E, norms=F), Z.ENODEV)]
+    for kw, status in cases:
+        with pytest.raises(Z.Z4cError) as e:
+            p.step(regs, None, Z.RK4, 0.1, Z.GHOST_NONE, flags=Z.STEP_MONITOR, **kw)
+        assert e.value.status == status, (kw, e.value)
+    p.close()
+    for kw in (dict(arith=Z.ARITH_FP32), dict(advection=Z.ADVECT_LOPSIDED)):
+        q = _plan(bt, **kw)
+        with pytest.raises(Z.Z4cError) as e:
+            q.step(regs, None, Z.RK4, 0.1, Z.GHOST_NONE, flags=Z.STEP_MONITOR, cons=E, norms=F)
+        assert e.value.status == Z.ENOTSUP, kw
+        q.close()

@@ -133,3 +133,38 @@ def test_level_set_monitor_matches_constraints():
             scale = np.abs(r).max()
             assert np.abs(x - r).max() <= 1e-9 * scale + 1e-300, (b, q, np.abs(x - r).max(), scale)
     np.testing.assert_allclose(nm, nc, rtol=1e-9, atol=1e-300)
+
+
+def test_graph_step_with_monitor():
+    """Z4C_STEP_MONITOR in the graph-replayed RK4 step of the level set: each
+    of three replays (eager work and synchronisation between them) gives the
+    norms of z4c_constraints on the state it started from (within 1e-9), and
+    the same state as the step without the monitor (within 1e-13)."""
+    bt = W.config4()
+    note(f"graph step with monitor: {bt.name}")
+    Zm = Z()
+    plan = Zm.plan_for(bt)
+    u0 = dev(bt.u)
+    plan.ghost_fill(Zm.GHOST_PERIODIC, u0)
+    nb = len(bt.blocks)
+    regs = [u0.clone(), u0.clone(), u0.clone(), torch.zeros_like(u0)]
+    ref = [u0.clone(), u0.clone(), u0.clone(), torch.zeros_like(u0)]
+    cons = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+    norms = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+    cons_c = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+    norms_c = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+    for rep in range(3):
+        plan.set_halo(Zm.GHOST_PERIODIC)
+        plan.constraints(regs[0], None, cons_c, norms_c)
+        want = host(norms_c).copy()
+        r = plan.step(regs, None, Zm.RK4, bt.dt, Zm.GHOST_PERIODIC, graph=True,
+                      flags=Zm.STEP_MONITOR, cons=cons, norms=norms)
+        r2 = plan.step(ref, None, Zm.RK4, bt.dt, Zm.GHOST_PERIODIC, graph=True)
+        assert r == r2 == 0
+        got = host(norms)
+        np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-300)
+        a, b = host(regs[0]), host(ref[0])
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+        note(f"  replay {rep}: norms within 1e-9, state max diff {np.abs(a - b).max():.3g}")
+        ref[0].copy_(regs[0])     # both continue from the same state
+    plan.close()
