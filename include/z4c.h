@@ -306,6 +306,40 @@ z4c_status z4c_xplan_create(const z4c_plan *plan, const z4c_transfer *prolong, i
                             z4c_xplan **out);
 z4c_status z4c_xplan_destroy(z4c_xplan *xplan);
 
+/* Where a block sits in an AMR level set: its refinement level and the
+ * position of its interior vertex 0 on the integer lattice of the finest
+ * level present (lattice spacing = the spacing of level Lmax; a block of
+ * level L has its vertices 2^(Lmax - L) lattice units apart).  A block
+ * owns the lattice points of its span [o, o + n step) per direction: its
+ * interior vertices and, on a coarse level, the points between its last
+ * vertex and the next block; the spans of a level set tile it. */
+typedef struct {
+    int level;
+    int o[3];
+} z4c_loc;
+
+/* The transfers of a ghost exchange across the level jump between level
+ * `coarse_level` and coarse_level + 1 (Sec. 3.2, vertex-centred refinement
+ * by 2), from the blocks of `plan` and their places `locs` (HOST, nblocks
+ * entries):
+ *   prolongation: every ghost point of a fine block in the span of a coarse
+ *     block, one transfer per (fine block, ghost region of the 26, coarse
+ *     block) with a non-empty intersection;
+ *   restriction: every ghost point of a coarse block in the span of a fine
+ *     block (an interior vertex of it), likewise per (coarse block, ghost
+ *     region, fine block).
+ * Ghost points owned by blocks of the same level are the neighbour ghost
+ * fill's; points no block owns are left alone.  Use: restrict, refresh the
+ * coarse level's same-level ghosts, prolongate (coarse level pairs first).
+ * The arrays are filled up to max_prolong / max_restrict entries; *nprolong
+ * and *nrestrict receive the counts needed (call with max = 0 to size
+ * them; Z4C_EINVAL when an array is too small).  Errors: a fine block whose
+ * vertex 0 is not a coarse lattice vertex, levels outside 0..30, or block
+ * spacings that do not halve per level (Z4C_EINVAL). */
+z4c_status z4c_level_transfers(const z4c_plan *plan, const z4c_loc *locs, int coarse_level,
+                               z4c_transfer *prolong, int max_prolong, int *nprolong,
+                               z4c_transfer *restrict_, int max_restrict, int *nrestrict);
+
 /* Apply every prolongation (or every restriction) of `xplan` to the state
  * array `u` (device, the plan's layout), asynchronously on the stream. */
 z4c_status z4c_prolongate(const z4c_xplan *xplan, double *u, void *hip_stream);

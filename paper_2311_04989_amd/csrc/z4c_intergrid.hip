@@ -557,6 +557,120 @@ static z4c_status xcall(const z4c_xplan *X, double *u, bool pro, hipStream_t s)
     return e == hipSuccess ? Z4C_OK : set_hip_error(e, "intergrid kernel launch");
 }
 
+z4c_status z4c_level_transfers(const z4c_plan *plan, const z4c_loc *locs, int coarse_level,
+                               z4c_transfer *prolong, int max_prolong, int *nprolong,
+                               z4c_transfer *restrict_, int max_restrict, int *nrestrict)
+{
+    if (!plan || !locs || !nprolong || !nrestrict)
+        return set_error(Z4C_EINVAL, "plan, locs and the counts must not be NULL");
+    if (max_prolong < 0 || max_restrict < 0 || (max_prolong > 0 && !prolong)
+        || (max_restrict > 0 && !restrict_))
+        return set_error(Z4C_EINVAL, "bad output arrays");
+    *nprolong = *nrestrict = 0;
+    const std::vector<z4c_block> &B = plan_blocks(plan);
+    const int nb = (int)B.size();
+    int lmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (locs[b].level < 0 || locs[b].level > 30)
+            return set_error(Z4C_EINVAL, "levels must be in 0..30");
+        lmax = std::max(lmax, locs[b].level);
+    }
+    if (coarse_level < 0 || coarse_level + 1 > lmax)
+        return set_error(Z4C_EINVAL, "coarse_level + 1 must be a level of the set");
+    // lattice step of a level, and the checks of the pairs used
+    auto step = [lmax](int L) { return 1LL << (lmax - L); };
+    std::vector<int> cs, fs;
+    for (int b = 0; b < nb; ++b) {
+        if (locs[b].level == coarse_level)
+            cs.push_back(b);
+        else if (locs[b].level == coarse_level + 1)
+            fs.push_back(b);
+    }
+    const long long sc = step(coarse_level), sf = step(coarse_level + 1);
+    for (int c : cs)
+        for (int f : fs) {
+            if (!same_ratio(B[c].dx, B[f].dx) || !same_ratio(B[c].dy, B[f].dy)
+                || !same_ratio(B[c].dz, B[f].dz))
+                return set_error(Z4C_EINVAL, "block spacings do not halve from the coarse to "
+                                             "the fine level");
+            for (int d = 0; d < 3; ++d)
+                if (((long long)locs[f].o[d] - locs[c].o[d]) % sc != 0)
+                    return set_error(Z4C_EINVAL, "a fine block's vertex 0 is not a coarse "
+                                                 "lattice vertex");
+        }
+    // ghost region r of a block (26, no interior): per direction -1, 0, +1
+    auto region = [](const z4c_block &K, int r, int lo[3], int hi[3]) {
+        const int n[3] = {K.nx, K.ny, K.nz};
+        const int q[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = q[d] < 0 ? -K.ng : (q[d] == 0 ? 0 : n[d]);
+            hi[d] = q[d] < 0 ? 0 : (q[d] == 0 ? n[d] : n[d] + K.ng);
+        }
+        return !(q[0] == 0 && q[1] == 0 && q[2] == 0);
+    };
+    // floor and ceiling of a / b, b > 0
+    auto fdiv = [](long long a, long long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    auto cdiv = [&fdiv](long long a, long long b) { return -fdiv(-a, b); };
+    int np = 0, nr = 0;
+    for (int f : fs)
+        for (int c : cs) {
+            const z4c_block &F = B[f], &C = B[c];
+            const int nC[3] = {C.nx, C.ny, C.nz}, nF[3] = {F.nx, F.ny, F.nz};
+            int c0[3];
+            for (int d = 0; d < 3; ++d)
+                c0[d] = (int)(((long long)locs[f].o[d] - locs[c].o[d]) / sc);
+            for (int r = 0; r < 27; ++r) {
+                int lo[3], hi[3];
+                // prolongation: ghost points of F in C's span [o, o + n step)
+                if (region(F, r, lo, hi)) {
+                    bool ok = true;
+                    z4c_transfer T{c, f, {c0[0], c0[1], c0[2]}, {0, 0, 0}, {0, 0, 0}};
+                    for (int d = 0; d < 3 && ok; ++d) {
+                        const long long a = locs[c].o[d] - (long long)locs[f].o[d];
+                        const long long i0 = std::max<long long>(lo[d], cdiv(a, sf));
+                        const long long i1 = std::min<long long>(
+                            hi[d], fdiv(a + (long long)nC[d] * sc - 1, sf) + 1);
+                        ok = i0 < i1;
+                        T.lo[d] = (int)i0;
+                        T.hi[d] = (int)i1;
+                    }
+                    if (ok) {
+                        if (np < max_prolong)
+                            prolong[np] = T;
+                        ++np;
+                    }
+                }
+                // restriction: ghost points of C in F's span (all its vertices)
+                if (region(C, r, lo, hi)) {
+                    bool ok = true;
+                    z4c_transfer T{c, f, {c0[0], c0[1], c0[2]}, {0, 0, 0}, {0, 0, 0}};
+                    for (int d = 0; d < 3 && ok; ++d) {
+                        const long long a = locs[f].o[d] - (long long)locs[c].o[d];
+                        const long long j0 = std::max<long long>(lo[d], cdiv(a, sc));
+                        const long long j1 = std::min<long long>(
+                            hi[d], fdiv(a + (long long)(nF[d] - 1) * sf, sc) + 1);
+                        ok = j0 < j1;
+                        T.lo[d] = (int)j0;
+                        T.hi[d] = (int)j1;
+                    }
+                    if (ok) {
+                        if (nr < max_restrict)
+                            restrict_[nr] = T;
+                        ++nr;
+                    }
+                }
+            }
+        }
+    *nprolong = np;
+    *nrestrict = nr;
+    if (np > max_prolong || nr > max_restrict)
+        return (max_prolong == 0 && max_restrict == 0)
+                   ? Z4C_OK
+                   : set_error(Z4C_EINVAL, "output arrays too small (counts in *nprolong, "
+                                           "*nrestrict)");
+    return Z4C_OK;
+}
+
 z4c_status z4c_prolongate(const z4c_xplan *X, double *u, void *stream)
 {
     return xcall(X, u, true, (hipStream_t)stream);

@@ -161,8 +161,14 @@ def lib():
                                        ctypes.c_int, ctypes.POINTER(vp)]
         L.z4c_xplan_destroy.argtypes = [vp]
         L.z4c_prolongate.argtypes = [vp, vp, vp]
+        L.z4c_level_transfers.argtypes = [vp, ctypes.POINTER(Loc), ctypes.c_int,
+                                          ctypes.POINTER(Transfer), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(Transfer), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]
         L.z4c_restrict.argtypes = [vp, vp, vp]
-        for name in ("z4c_xplan_create", "z4c_xplan_destroy", "z4c_prolongate", "z4c_restrict"):
+        for name in ("z4c_xplan_create", "z4c_xplan_destroy", "z4c_prolongate", "z4c_restrict",
+                     "z4c_level_transfers"):
             getattr(L, name).restype = st
         for name in ("z4c_mplan_create", "z4c_mplan_destroy", "z4c_metric_to_cc",
                      "z4c_adm_sources", "z4c_sources_to_vc", "z4c_p2c", "z4c_c2p"):
@@ -400,6 +406,29 @@ def c2p_params(mhd=1, gamma_ad=2.0, chi_floor=1e-6, rho_atm=1e-13, p_atm=None, f
 
 def mplan_for(mbatch, flags: int = 0) -> MPlan:
     return MPlan(mbatch.table(), flags)
+
+
+class Loc(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("o", ctypes.c_int * 3)]
+
+
+def level_transfers(plan: "Plan", locs, coarse_level: int):
+    """z4c_level_transfers: (prolongations, restrictions) of the level jump
+    coarse_level -> coarse_level + 1 as lists of dicts (coarse, fine, c0, lo,
+    hi), from locs = [(level, (ox, oy, oz)), ...] per block of the plan."""
+    L = (Loc * len(locs))()
+    for b, (lev, o) in enumerate(locs):
+        L[b] = Loc(int(lev), (ctypes.c_int * 3)(*[int(v) for v in o]))
+    np_, nr = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().z4c_level_transfers(plan._h, L, int(coarse_level), None, 0, ctypes.byref(np_),
+                                     None, 0, ctypes.byref(nr)))
+    P = (Transfer * max(np_.value, 1))()
+    R = (Transfer * max(nr.value, 1))()
+    _check(lib().z4c_level_transfers(plan._h, L, int(coarse_level), P, np_.value,
+                                     ctypes.byref(np_), R, nr.value, ctypes.byref(nr)))
+    conv = lambda t: dict(coarse=t.coarse, fine=t.fine, c0=list(t.c0), lo=list(t.lo),  # noqa: E731
+                          hi=list(t.hi))
+    return [conv(P[k]) for k in range(np_.value)], [conv(R[k]) for k in range(nr.value)]
 
 
 def make_transfers(items):
