@@ -1180,6 +1180,11 @@ stage_kernel(const StageArgs a)
     constexpr int GU0 = 0, DB0 = GU_SLOT ? 18 : 0;
     constexpr int NSLOT = (GU_SLOT ? 18 : 0) + (DB_SLOT ? 9 : 0);
     __shared__ R slots[NSLOT > 0 ? NSLOT * NT : 1];
+    // Monitor: where the LDS left after the slots holds 8 doubles per thread,
+    // each constraint value waits there and the 16 wave sums run together at
+    // the end of the tile (independent chains) instead of one pair at a time.
+    constexpr bool MSTORE = MON && (SLOT_BUDGET - NSLOT) * (int)sizeof(R) >= 8 * (int)sizeof(double);
+    __shared__ double mval[MSTORE ? 8 * NT : 1];
 
     const int t = threadIdx.x;
     const int tx = t % TX, ty = (t / TX) % TY, tz = t / (TX * TY);
@@ -1361,15 +1366,19 @@ stage_kernel(const StageArgs a)
             const double c = active ? double(c_r) : 0.0;
             if (active && cb)
                 at(cb + q * fs, upt8) = c;
-            double v1 = fabs(c), v2 = c * c;
+            if constexpr (MSTORE) {
+                mval[q * NT + t] = c;
+            } else {
+                double v1 = fabs(c), v2 = c * c;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                v1 += __shfl_xor(v1, off, 64);
-                v2 += __shfl_xor(v2, off, 64);
-            }
-            if ((t & 63) == 0) {
-                mred[(t >> 6) * 16 + 2 * q] = v1;
-                mred[(t >> 6) * 16 + 2 * q + 1] = v2;
+                for (int off = 32; off >= 1; off >>= 1) {
+                    v1 += __shfl_xor(v1, off, 64);
+                    v2 += __shfl_xor(v2, off, 64);
+                }
+                if ((t & 63) == 0) {
+                    mred[(t >> 6) * 16 + 2 * q] = v1;
+                    mred[(t >> 6) * 16 + 2 * q + 1] = v2;
+                }
             }
         };
 
@@ -1834,6 +1843,26 @@ stage_kernel(const StageArgs a)
                 constexpr int ii = decltype(I_c)::value;
                 mon(std::integral_constant<int, C_MX + ii>{}, Mc[ii]);
             });
+            if constexpr (MSTORE) {   // the values this thread parked, summed per wave
+                double v[16];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double c = mval[q * NT + t];
+                    v[2 * q] = fabs(c);
+                    v[2 * q + 1] = c * c;
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        v[q] += __shfl_xor(v[q], off, 64);
+                }
+                if ((t & 63) == 0) {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        mred[(t >> 6) * 16 + q] = v[q];
+                }
+            }
             __syncthreads();
             // per-tile sums, the waves in order (as the constraint kernel)
             if (t < 16) {
