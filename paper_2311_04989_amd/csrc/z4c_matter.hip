@@ -410,11 +410,18 @@ struct Master {
 // Illinois iterations for a sign change of fn on [lo, hi] (fn(lo) < 0 <=
 // fn(hi)), every eighth step a bisection (the bracket shrinks whatever fn
 // does); converged when the bracket is narrower than tol * hi or one ulp;
-// returns false after max_iter steps without convergence.
+// returns false after max_iter steps without convergence.  An end where fn
+// is exactly zero is the root: cold gas puts the master function's root on
+// the bracket end mu+, where the secant step cannot move and only
+// bisections would remain.
 template <typename Fn>
 __device__ __forceinline__ bool illinois(Fn fn, double lo, double hi, double flo, double fhi,
                                          double tol, int max_iter, double &root)
 {
+    if (fhi == 0.0 || flo == 0.0) {
+        root = fhi == 0.0 ? hi : lo;
+        return true;
+    }
     int side = 0;
     for (int it = 0; it < max_iter; ++it) {
         double m = (lo * fhi - hi * flo) / (fhi - flo);
