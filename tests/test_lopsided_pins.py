@@ -1,6 +1,6 @@
 """Pins of the lopsided advection stencil of the oracle (CPU only).
 
-The paper names no advection stencil; the lopsided reading is
+The paper names no advection stencil; the lopsided reading taken here is
 the first derivative of order p on the p + 1 points shifted by one towards
 the sign of beta^k, whose weights are fixed by exactness on polynomials of
 degree <= p.  Pinned here without the oracle's own solve:
