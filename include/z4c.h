@@ -54,7 +54,7 @@ typedef enum {
     Z4C_ENOGHOST = -2,  /* ng < fd_order/2 + 1 for some block                  */
     Z4C_EALIGN = -3,    /* array pointer not 8-byte aligned                    */
     Z4C_EHIP = -4,      /* a HIP runtime call or kernel launch failed          */
-    Z4C_ENOTSUP = -5,   /* valid request this build does not implement         */
+    Z4C_ENOTSUP = -5,   /* valid request the library does not implement      */
     Z4C_ENOMEM = -6,    /* device allocation for plan tables failed            */
     Z4C_ENODEV = -7     /* plan created without a device cannot launch         */
 } z4c_status;
