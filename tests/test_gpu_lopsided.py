@@ -127,3 +127,38 @@ def test_lopsided_neighbour_halo():
     for b in range(len(bt.blocks)):
         for f in range(W.NF):
             assert np.array_equal(bt.interior(got, b, f), bt.interior(ref, b, f)), (b, f)
+
+
+def test_level_set_lopsided_stage_sampled():
+    """At full size in the launch configuration the benchmark times: the
+    uneven level set (1,024 blocks, ghosts read through the periodic rule,
+    autotuned shapes), lopsided advection, RK4 stage 2; 16 sampled blocks
+    (4 of each size) against the oracle."""
+    bt = W.config4()
+    O.ghost_fill(bt, bt.u)                   # stored ghosts = the periodic rule
+    bt.params.advection = 1
+    note(f"lopsided level set: {bt.name}")
+    Zm = Z()
+    plan = Zm.plan_for(bt)
+    u0 = dev(bt.u)
+    plan.set_halo(Zm.GHOST_PERIODIC)
+    out, u1 = u0.clone(), torch.zeros_like(u0)
+    plan.autotune(u0, out, u1, None, reps=2)
+    out, u1 = u0.clone(), torch.zeros_like(u0)
+    plan.rk_stage(u0, out, u1, u0, None, Zm.RK4[1], bt.dt)
+    got = host(out)
+    plan.close()
+    sizes = np.array([b.nx for b in bt.blocks])
+    rng = np.random.default_rng(4)
+    idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0], size=4, replace=False)
+                          for s in (8, 16, 24, 32)])
+    sub = bt.subset(idx)
+    o64, o80 = sub.u.copy(), sub.u.copy()
+    O.rk_stage(sub, sub.u, o64, np.zeros_like(sub.u), sub.u, O.RK4[1], bt.dt)
+    O.rk_stage(sub, sub.u, o80, np.zeros_like(sub.u), sub.u, O.RK4[1], bt.dt, ext=True)
+    gsub = bt.subset(idx)
+    for j, i in enumerate(idx):
+        for f in range(W.NF):
+            gsub.view(gsub.u, j, f)[...] = bt.view(got, i, f)
+    rows = compare(sub, gsub.u, o64, o80, base=sub.u)
+    assert_parity(rows, "lopsided level set sampled stage\n" + report(rows))

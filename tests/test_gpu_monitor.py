@@ -168,3 +168,39 @@ def test_graph_step_with_monitor():
         note(f"  replay {rep}: norms within 1e-9, state max diff {np.abs(a - b).max():.3g}")
         ref[0].copy_(regs[0])     # both continue from the same state
     plan.close()
+
+
+def test_level_set_monitor_sampled_against_oracle():
+    """At full size in the benchmark's launch configuration (autotuned
+    shapes, ghosts through the periodic rule), RK4 stage 2 with the monitor:
+    the constraints and per-block norms of 16 sampled blocks (4 of each
+    size) against the oracle's."""
+    bt = W.config4()
+    O.ghost_fill(bt, bt.u)
+    note(f"monitor level set vs oracle: {bt.name}")
+    Zm = Z()
+    plan = Zm.plan_for(bt)
+    u0 = dev(bt.u)
+    plan.set_halo(Zm.GHOST_PERIODIC)
+    out, u1 = u0.clone(), torch.zeros_like(u0)
+    plan.autotune(u0, out, u1, None, reps=2)
+    nb = len(bt.blocks)
+    cons = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+    norms = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+    plan.rk_stage_monitor(u0, out, u1, u0, None, Zm.RK4[1], bt.dt, cons, norms)
+    gc, gn = host(cons), host(norms).reshape(nb, 8, 2)
+    plan.close()
+    sizes = np.array([b.nx for b in bt.blocks])
+    rng = np.random.default_rng(6)
+    idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0], size=4, replace=False)
+                          for s in (8, 16, 24, 32)])
+    sub = bt.subset(idx)
+    c64, _ = O.constraints(sub)
+    c80, n80 = O.constraints(sub, ext=True)
+    gsub = np.zeros_like(c64)
+    for j, i in enumerate(idx):
+        for q in range(W.NC):
+            sub.view(gsub, j, q, W.NC)[...] = bt.view(gc, i, q, W.NC)
+    rows = compare(sub, gsub, c64, c80, nfields=W.NC)
+    assert_parity(rows, "monitor level set sampled constraints\n" + report(rows))
+    np.testing.assert_allclose(gn[idx], n80.reshape(len(idx), 8, 2), rtol=1e-10, atol=1e-300)
