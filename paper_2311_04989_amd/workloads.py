@@ -768,32 +768,43 @@ def level_jump(seed_offset: int = 7, ncoarse: int = 64, n: int = 16, ng: int = 4
 
 
 def refined_level_set(n: int = 8, ng: int = 4, grid=(3, 2, 2), refine=(1, 0, 0),
-                      h0: float = 1.0 / 16.0):
+                      h0: float = 1.0 / 16.0, refine2=None):
     """An AMR level set with one level jump: level-0 blocks of n^3 points
     (spacing h0) on a grid of grid[0] x grid[1] x grid[2] blocks, the one at
     `refine` replaced by its 8 children (level 1, spacing h0 / 2, n^3
-    points each).  Positions on the integer lattice of level 1 (step 2 for
-    level 0, 1 for level 1): block vertex i sits at lattice o + i * step.
-    Returns (batch, locs) with locs[b] = (level, o); the state is zero."""
+    points each); with `refine2` (0..7) that child replaced in turn by its 8
+    children (level 2).  Positions on the integer lattice of the finest
+    level (step 2^(Lmax - L) for level L): block vertex i sits at lattice
+    o + i * step.  Returns (batch, locs) with locs[b] = (level, o); the state
+    is zero."""
+    lmax = 1 if refine2 is None else 2
+    st = [1 << (lmax - L) for L in range(lmax + 1)]
+    hl = h0 / st[0]                       # spacing of the lattice
     blocks, locs = [], []
+
+    def add(level, o):
+        h = h0 / (1 << level)
+        blocks.append(Block(n, n, n, ng, h, h, h, o[0] * hl, o[1] * hl, o[2] * hl))
+        locs.append((level, o))
+
     for gz in range(grid[2]):
         for gy in range(grid[1]):
             for gx in range(grid[0]):
-                o = (2 * n * gx, 2 * n * gy, 2 * n * gz)
-                if (gx, gy, gz) == tuple(refine):
-                    continue
-                blocks.append(Block(n, n, n, ng, h0, h0, h0, o[0] * h0 / 2, o[1] * h0 / 2,
-                                    o[2] * h0 / 2))
-                locs.append((0, o))
+                if (gx, gy, gz) != tuple(refine):
+                    add(0, (n * st[0] * gx, n * st[0] * gy, n * st[0] * gz))
     r = tuple(refine)
     for m in range(8):
         mx, my, mz = m & 1, (m >> 1) & 1, (m >> 2) & 1
-        o = (2 * n * r[0] + n * mx, 2 * n * r[1] + n * my, 2 * n * r[2] + n * mz)
-        blocks.append(Block(n, n, n, ng, h0 / 2, h0 / 2, h0 / 2, o[0] * h0 / 2, o[1] * h0 / 2,
-                            o[2] * h0 / 2))
-        locs.append((1, o))
+        o = (n * st[0] * r[0] + n * st[1] * mx, n * st[0] * r[1] + n * st[1] * my,
+             n * st[0] * r[2] + n * st[1] * mz)
+        if m != refine2:
+            add(1, o)
+            continue
+        for m2 in range(8):
+            ax, ay, az = m2 & 1, (m2 >> 1) & 1, (m2 >> 2) & 1
+            add(2, (o[0] + n * st[2] * ax, o[1] + n * st[2] * ay, o[2] + n * st[2] * az))
     bt = Batch(blocks)
     bt.params = Params(fd_order=6)
     bt.name = (f"level set {grid[0]}x{grid[1]}x{grid[2]} blocks of {n}^3+{ng}g, block {refine} "
-               f"refined into 8")
+               f"refined into 8" + ("" if refine2 is None else f", child {refine2} again"))
     return bt, locs

@@ -154,16 +154,16 @@ def test_level_jump_at_scale_sampled():
             assert np.array_equal(bt.interior(got, b, f), bt.interior(bt.u, b, f))
 
 
-@pytest.mark.parametrize("refine", [(1, 0, 0), (0, 1, 1)])
-def test_level_jump_exchange_exact_on_polynomials(refine):
+@pytest.mark.parametrize("refine,refine2", [((1, 0, 0), None), ((0, 1, 1), None), ((1, 0, 0), 7)])
+def test_level_jump_exchange_exact_on_polynomials(refine, refine2):
     """The exchange z4c_level_transfers describes, run on the GPU: every
-    stored point of a level set with one refined block holds a polynomial of
-    degree <= 5 per direction except the destinations of the transfers,
-    which hold NaN; after z4c_restrict then z4c_prolongate (order 6) every
-    stored point holds the polynomial (exact up to rounding), so every
-    destination was written and no prolongation read a point before the
-    restriction filled it."""
-    bt, locs = W.refined_level_set(refine=refine)
+    stored point of a level set with one or two level jumps holds a
+    polynomial of degree <= 5 per direction except the destinations of the
+    transfers, which hold NaN; after the restrictions (finest level pair
+    first) and the prolongations (order 6, coarsest pair first) every stored
+    point holds the polynomial (exact up to rounding), so every destination
+    was written and no transfer read a point before it was filled."""
+    bt, locs = W.refined_level_set(refine=refine, refine2=refine2)
     poly = lambda x, y, z: (x ** 5 - 0.3 * x ** 2 + 0.7) * (y ** 5 + 0.2 * y - 1.1) \
         * (z ** 4 + 0.5 * z ** 3 - 0.25)   # noqa: E731
     want = np.zeros_like(bt.u)
@@ -172,21 +172,28 @@ def test_level_jump_exchange_exact_on_polynomials(refine):
         for f in range(W.NF):
             bt.view(want, b, f)[...] = poly(X, Y, Zc) + f
     plan = Z().plan_for(bt)
-    pro, res = Z().level_transfers(plan, locs, 0)
-    note(f"level-jump exchange {refine}: {len(pro)} prolongations, {len(res)} restrictions")
+    pairs = range(max(L for L, _ in locs))
+    sets = [Z().level_transfers(plan, locs, L) for L in pairs]
+    note(f"level-jump exchange {refine} {refine2}: "
+         + ", ".join(f"pair {L}: {len(p)} prolongations, {len(r)} restrictions"
+                     for L, (p, r) in zip(pairs, sets)))
     start = want.copy()
-    for t, key in [(t, "fine") for t in pro] + [(t, "coarse") for t in res]:
-        b, g = t[key], bt.blocks[t[key]].ng
-        sl = tuple(slice(t["lo"][d] + g, t["hi"][d] + g) for d in (2, 1, 0))
-        for f in range(W.NF):
-            bt.view(start, b, f)[sl] = np.nan
-    xp = Z().XPlan(plan, pro, res, 6)
+    for pro, res in sets:
+        for t, key in [(t, "fine") for t in pro] + [(t, "coarse") for t in res]:
+            b, g = t[key], bt.blocks[t[key]].ng
+            sl = tuple(slice(t["lo"][d] + g, t["hi"][d] + g) for d in (2, 1, 0))
+            for f in range(W.NF):
+                bt.view(start, b, f)[sl] = np.nan
+    xps = [Z().XPlan(plan, pro, res, 6) for pro, res in sets]
     u = torch.from_numpy(start).to(DEV)
-    xp.restrict(u)
-    xp.prolongate(u)
+    for xp in reversed(xps):
+        xp.restrict(u)
+    for xp in xps:
+        xp.prolongate(u)
     torch.cuda.synchronize()
     got = u.cpu().numpy()
-    xp.close()
+    for xp in xps:
+        xp.close()
     plan.close()
     assert np.isfinite(got).all()
     scale = np.abs(want).max()

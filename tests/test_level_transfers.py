@@ -17,11 +17,15 @@ def _plan(bt):
     return Z.Plan(Z.make_params(bt.params), Z.make_blocks(bt.block_table()), Z.PLAN_NO_DEVICE)
 
 
+def step(locs, lev):
+    return 1 << (max(L for L, _ in locs) - lev)
+
+
 def owner(bt, locs, X):
     """Block whose span [o, o + n step) holds lattice point X (the spans
     tile the level set), or None outside it."""
     found = [b for b, (blk, (lev, o)) in enumerate(zip(bt.blocks, locs))
-             if all(o[d] <= X[d] < o[d] + n * (2 if lev == 0 else 1)
+             if all(o[d] <= X[d] < o[d] + n * step(locs, lev)
                     for d, n in enumerate((blk.nx, blk.ny, blk.nz)))]
     assert len(found) <= 1, (X, found)
     return (found[0], None) if found else (None, None)
@@ -50,27 +54,32 @@ def covered(transfers, dest_key):
     return out
 
 
-@pytest.mark.parametrize("refine", [(1, 0, 0), (0, 1, 1)])
-def test_transfers_match_ownership(refine):
-    bt, locs = W.refined_level_set(refine=refine)
+@pytest.mark.parametrize("refine,refine2,pair", [((1, 0, 0), None, 0), ((0, 1, 1), None, 0),
+                                                 ((1, 0, 0), 7, 0), ((1, 0, 0), 7, 1)])
+def test_transfers_match_ownership(refine, refine2, pair):
+    bt, locs = W.refined_level_set(refine=refine, refine2=refine2)
     plan = _plan(bt)
-    pro, res = Z.level_transfers(plan, locs, 0)
+    pro, res = Z.level_transfers(plan, locs, pair)
     P, R = covered(pro, "fine"), covered(res, "coarse")
     want_p, want_r = set(), set()
     for b, (blk, (lev, o)) in enumerate(zip(bt.blocks, locs)):
-        s = 2 if lev == 0 else 1
+        if lev not in (pair, pair + 1):
+            continue
+        s = step(locs, lev)
         for (i, j, k) in ghost_points(blk):
             X = (o[0] + i * s, o[1] + j * s, o[2] + k * s)
             ob, _ = owner(bt, locs, X)
-            if ob is None or locs[ob][0] == lev:
+            if ob is None:
                 continue
-            if lev == 1:                      # fine ghost in a coarse interior
+            lo_ = locs[ob][0]
+            if lev == pair + 1 and lo_ == pair:     # fine ghost in a coarse span
                 want_p.add((b, i, j, k))
                 t = P[(b, i, j, k)]
                 assert t["coarse"] == ob
                 oc = locs[ob][1]
-                assert [(o[d] - oc[d]) // 2 for d in range(3)] == t["c0"]
-            else:                             # coarse ghost on a fine interior vertex
+                sc = step(locs, pair)
+                assert [(o[d] - oc[d]) // sc for d in range(3)] == t["c0"]
+            elif lev == pair and lo_ == pair + 1:   # coarse ghost in a fine span
                 want_r.add((b, i, j, k))
                 assert R[(b, i, j, k)]["fine"] == ob
     assert want_p == set(P) and want_r == set(R)
