@@ -204,3 +204,40 @@ def test_level_set_monitor_sampled_against_oracle():
     rows = compare(sub, gsub, c64, c80, nfields=W.NC)
     assert_parity(rows, "monitor level set sampled constraints\n" + report(rows))
     np.testing.assert_allclose(gn[idx], n80.reshape(len(idx), 8, 2), rtol=1e-10, atol=1e-300)
+
+
+def test_eager_step_with_monitor_and_stored_ghosts():
+    """Z4C_STEP_MONITOR with Z4C_STEP_STORED_GHOSTS (stage 0 reads stored
+    ghosts, refreshed by the step after each stage), eager: the norms equal
+    those of z4c_constraints on the state the step started from (within
+    1e-9), the state equals the monitor-free step's (within 1e-13), and the
+    constraint fields are written."""
+    bt = W.config4()
+    note(f"eager stored-ghost step with monitor: {bt.name}")
+    Zm = Z()
+    plan = Zm.plan_for(bt)
+    u0 = dev(bt.u)
+    plan.ghost_fill(Zm.GHOST_PERIODIC, u0)
+    nb = len(bt.blocks)
+    cons_c = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+    norms_c = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+    plan.constraints(u0, None, cons_c, norms_c)
+    want = host(norms_c).copy()
+    regs = [u0.clone(), u0.clone(), u0.clone(), torch.zeros_like(u0)]
+    ref = [u0.clone(), u0.clone(), u0.clone(), torch.zeros_like(u0)]
+    cons = torch.full((bt.total_c,), float("nan"), dtype=torch.float64, device=DEV)
+    norms = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+    flags = Zm.STEP_MONITOR | Zm.STEP_STORED_GHOSTS
+    r = plan.step(regs, None, Zm.RK4, bt.dt, Zm.GHOST_PERIODIC, flags=flags, cons=cons,
+                  norms=norms)
+    r2 = plan.step(ref, None, Zm.RK4, bt.dt, Zm.GHOST_PERIODIC, flags=Zm.STEP_STORED_GHOSTS)
+    np.testing.assert_allclose(host(norms), want, rtol=1e-9, atol=1e-300)
+    a, b = host(regs[r]), host(ref[r2])
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    gc, cc = host(cons), host(cons_c)
+    for blk in range(0, nb, 97):
+        for q in range(W.NC):
+            x, y = bt.interior(gc, blk, q, W.NC), bt.interior(cc, blk, q, W.NC)
+            assert np.isfinite(x).all()
+            assert np.abs(x - y).max() <= 1e-9 * np.abs(y).max() + 1e-300
+    plan.close()
