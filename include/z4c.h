@@ -6,9 +6,9 @@
  * the Z4c formulation of the Einstein equations with matter sources (Sec. 2:
  * the spacetime is evolved in Z4c with the perfect-fluid ADM projections
  * rho, S_i, S_ij as sources), discretised with centred finite differences of
- * order 4 or 6 and Kreiss-Oliger dissipation (Sec. 4.1: 6th-order FD,
+ * order 4 or 6 and Kreiss-Oliger dissipation (opening paragraph of Sec. 4: 6th-order FD,
  * kappa1 = 0.02, kappa2 = 0, sigma_KO = 0.5), and advances it by one stage of
- * a low-storage Runge-Kutta method (Sec. 4.1: RK3; RK4 also supported).
+ * a low-storage Runge-Kutta method (same paragraph: RK3; RK4 also supported).
  *
  * Conventions
  *   - G = c = 1.  Every floating-point array is double (FP64) in device
@@ -71,10 +71,10 @@ typedef enum {
 } z4c_ghost;
 
 /* Scheme parameters.
- *   fd_order     4 or 6 (centred first/second derivatives, Sec. 4.1)
- *   ko_sigma     Kreiss-Oliger strength sigma (Sec. 4.1: 0.5); operator of
+ *   fd_order     4 or 6 (centred first/second derivatives; Sec. 4 uses 6)
+ *   ko_sigma     Kreiss-Oliger strength sigma (Sec. 4: 0.5); operator of
  *                order 2r = fd_order + 2, Q = (-1)^(r+1) sigma/(2^(2r) h) D^(2r)
- *   kappa1/2     Z4c constraint damping (Sec. 4.1: 0.02 / 0)
+ *   kappa1/2     Z4c constraint damping (Sec. 4: 0.02 / 0)
  *   eta          Gamma-driver damping
  *   lapse        1+log (d_t alpha = -2 alpha Khat + advection), harmonic
  *                (-alpha^2 Khat) or frozen (no lapse source term)

@@ -120,7 +120,7 @@ z4c_status z4c_adm_sources(const z4c_mplan *plan, const z4c_fluid *fluid, int ex
 z4c_status z4c_sources_to_vc(const z4c_mplan *plan, int order, const double *adm, double *matter,
                              void *hip_stream);
 
-/* Primitive recovery (Sec. 3.2, conservative-to-primitive inversion, and
+/* Primitive recovery (Sec. 3.5, conservative-to-primitive inversion, and
  * Appendix A).  Ideal gas p = (Gamma - 1) rho eps.  Per cell, with
  * gamma_ij = gt_ij / max(chi, chi_floor) from the CC geometry:
  *   - the conservatives are undensitised; if D / sqrt(gamma) < f_thr rho_atm
@@ -135,7 +135,7 @@ z4c_status z4c_sources_to_vc(const z4c_mplan *plan, int order, const double *adm
  *     ceiling), or with rho < f_thr rho_atm, becomes atmosphere (status 2 /
  *     status 1);
  *   - atmosphere: rho = rho_atm, ut^i = 0, p = p_atm, B unchanged, and the
- *     conservatives of that state written back (Sec. 3.2: atmosphere
+ *     conservatives of that state written back (Sec. 3.5: atmosphere
  *     treatment).  Status 0: recovered.
  * `prim` receives rho, ut^i, p and (mhd) the undensitised B^i. */
 typedef struct {

@@ -8,16 +8,17 @@
  * What it computes (one MeshBlock at a time, every interior point):
  *   - the Z4c right-hand side of the 22 evolved fields (the paper evolves
  *     the Einstein equations in the Z4c formulation with constraint damping
- *     kappa1, kappa2 and the moving-puncture gauge, Sec. 2 and Sec. 4.1; the
+ *     kappa1, kappa2 and the moving-puncture gauge, Sec. 2 and the opening
+ *     paragraph of Sec. 4; the
  *     equations themselves are those of the standard Z4c system the paper
  *     cites, written out below term by term),
- *   - centred finite differences of order 4 or 6 (Sec. 4.1: 6th order),
+ *   - centred finite differences of order 4 or 6 (Sec. 4: 6th order),
  *     mixed second derivatives as a first derivative of a first derivative,
  *   - Kreiss-Oliger dissipation of order 2r = p + 2 on every field
- *     (Sec. 4.1: sigma_KO = 0.5),
+ *     (Sec. 4: sigma_KO = 0.5),
  *   - ADM matter source terms rho, S_i, S_ij (Sec. 2.1, the perfect-fluid
  *     projections), taken here as given input arrays,
- *   - one low-storage Runge-Kutta stage (Sec. 4.1: RK3; RK4 also used) with
+ *   - one low-storage Runge-Kutta stage (Sec. 4: RK3; RK4 also used) with
  *     algebraic enforcement det(gt) = 1, tr(At) = 0 and chi/alpha floors,
  *   - the constraints H, M_i, Theta, Z^i and their L1/L2 norms
  *     (Sec. 4.1, constraint monitoring of the static star),

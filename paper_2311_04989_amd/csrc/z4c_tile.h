@@ -12,13 +12,13 @@
 // side are never all live together, and each field's Runge-Kutta update is
 // applied as soon as its right-hand side is complete.
 //
-// Stencils are centred, of order p = 4 or 6 (Sec. 4.1 uses 6), applied in
+// Stencils are centred, of order p = 4 or 6 (Sec. 4 uses 6), applied in
 // centre-subtracted form (u_m - u_-m, u_m - u_0), mixed second derivatives
 // as the first-derivative stencil applied along one axis to first
 // differences along the other; Kreiss-Oliger dissipation of order p + 2 on
-// every field (Sec. 4.1, sigma_KO).  The pointwise algebra is the standard
+// every field (Sec. 4, sigma_KO).  The pointwise algebra is the standard
 // Z4c system with constraint damping kappa1, kappa2 and the moving-puncture
-// gauge (Sec. 2, Sec. 4.1), with the perfect-fluid ADM sources rho, S_i,
+// gauge (Sec. 2, Sec. 4), with the perfect-fluid ADM sources rho, S_i,
 // S_ij (Sec. 2.1) as inputs.
 //
 // Arithmetic type R: double, or float with every stencil difference formed
