@@ -61,7 +61,7 @@ typedef enum {
 
 typedef enum { Z4C_LAPSE_1PLUSLOG = 0, Z4C_LAPSE_HARMONIC = 1, Z4C_LAPSE_FROZEN = 2 } z4c_lapse;
 typedef enum { Z4C_SHIFT_GAMMADRIVER = 0, Z4C_SHIFT_FROZEN = 1 } z4c_shift;
-typedef enum { Z4C_ARITH_FP64 = 0, Z4C_ARITH_FP32 = 1 } z4c_arith;
+typedef enum { Z4C_ARITH_FP64 = 0, Z4C_ARITH_FP32 = 1, Z4C_ARITH_FP32_NAIVE = 2 } z4c_arith;
 typedef enum { Z4C_ADVECT_CENTRED = 0, Z4C_ADVECT_LOPSIDED = 1 } z4c_advection;
 typedef enum {
     Z4C_GHOST_NONE = 0,       /* leave ghost values as they are               */
@@ -88,6 +88,12 @@ typedef enum {
  *                u_m - u_0 are formed in double, then the derivatives,
  *                dissipation and the pointwise algebra run in float; storage,
  *                the Runge-Kutta combination and the floors stay double.
+ *                FP32_NAIVE: float arithmetic with every sample rounded to
+ *                float before the stencil differences (the form that loses
+ *                perturbations below float resolution); right-hand side
+ *                only, order 6, centred advection, for precision
+ *                comparisons (Z4C_ENOTSUP for stages, steps, autotuning and
+ *                other orders).
  *   advection    stencil of the advection terms beta^k d_k u (every field):
  *                CENTRED (the fd_order first derivative) or LOPSIDED, the
  *                fd_order-accurate first derivative on the points shifted by

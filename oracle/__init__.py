@@ -24,12 +24,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "z4c_oracle.c")
 LIB = os.path.join(HERE, "libz4c_oracle.so")
 LIB_EXT = os.path.join(HERE, "libz4c_oracle_ext.so")
+# FP32-arithmetic references of the right-hand side: float algebra with the
+# stencil differences formed in double (mixed), or with the samples rounded to
+# float first (naive).  They measure what FP32 arithmetic itself costs.
+LIB_F32 = os.path.join(HERE, "libz4c_oracle_f32.so")
+LIB_F32N = os.path.join(HERE, "libz4c_oracle_f32n.so")
+_PATHS = {"f64": LIB, "ext": LIB_EXT, "f32": LIB_F32, "f32naive": LIB_F32N}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O3, OpenMP, no FMA contraction), once
-    with double and once with x87 extended precision as working type."""
-    for path, extra in ((LIB, []), (LIB_EXT, ["-DORACLE_EXTENDED"])):
+    """Compile the oracle with gcc (-O3, OpenMP, no FMA contraction), with
+    double as working type, with x87 extended precision, and the two FP32
+    references."""
+    for path, extra in ((LIB, []), (LIB_EXT, ["-DORACLE_EXTENDED"]), (LIB_F32, ["-DORACLE_FP32"]),
+                        (LIB_F32N, ["-DORACLE_FP32", "-DORACLE_NAIVE"])):
         if force or not os.path.exists(path):
             cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
                    "-fPIC", "-shared", "-Wall"] + extra + ["-o", path + ".tmp", SRC, "-lm"]
@@ -72,10 +80,12 @@ SSPRK3 = [
 _libs = {}
 
 
-def lib(ext: bool = False):
-    """The FP64 oracle, or (ext=True) the same source in extended precision."""
+def lib(ext=False):
+    """The FP64 oracle, or (ext=True) the same source in extended precision;
+    ext may also name a build: "f64", "ext", "f32", "f32naive"."""
+    ext = {False: "f64", True: "ext"}.get(ext, ext)
     if ext not in _libs:
-        path = LIB_EXT if ext else LIB
+        path = _PATHS[ext]
         if not os.path.exists(path):
             build(force=False)
         L = ctypes.CDLL(path)
@@ -123,8 +133,10 @@ def max_threads() -> int:
     return int(lib().orc_max_threads())
 
 
-def rhs(batch, u=None, params=None, nthreads: int = 0, ext: bool = False) -> np.ndarray:
-    """Right-hand side of all blocks; ghost entries of the result are 0."""
+def rhs(batch, u=None, params=None, nthreads: int = 0, ext=False) -> np.ndarray:
+    """Right-hand side of all blocks; ghost entries of the result are 0.
+    ext=True: extended precision; ext="f32" / "f32naive": the FP32-arithmetic
+    references (mixed / naive differences)."""
     u = batch.u if u is None else u
     out = np.zeros_like(u)
     tab = batch.block_table()

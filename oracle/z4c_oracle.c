@@ -34,7 +34,12 @@
  * sum rounds as written.  The working type `real` is double; the same source
  * built with -DORACLE_EXTENDED works in x87 extended precision (64-bit
  * significand) and serves only to measure the FP64 oracle's own rounding
- * error.  Arrays crossing the interface are always double.
+ * error.  Built with -DORACLE_FP32 the working type is float while every
+ * stencil difference is still formed in double (the FP32-arithmetic form of
+ * the right-hand side); adding -DORACLE_NAIVE rounds the samples to float
+ * before the differences.  These two builds measure what FP32 arithmetic
+ * itself costs in accuracy; only their right-hand side is used.  Arrays
+ * crossing the interface are always double.
  */
 #include <tgmath.h>
 #include <stdlib.h>
@@ -43,8 +48,10 @@
 #include <omp.h>
 #endif
 
-#ifdef ORACLE_EXTENDED
+#if defined(ORACLE_EXTENDED)
 typedef long double real;
+#elif defined(ORACLE_FP32)
+typedef float real;
 #else
 typedef double real;
 #endif
@@ -90,13 +97,21 @@ static const int SYM_J[6] = {0, 1, 2, 1, 2, 2};
 
 /* Input samples are double; every difference below is formed in `real`. */
 #define U(off) ((real)u[(off)])
+/* Difference of two samples.  In the FP32-arithmetic reference (ORACLE_FP32)
+ * it is formed in double and rounded to float afterwards (the mixed form);
+ * with ORACLE_NAIVE as well, from samples already rounded to float. */
+#if defined(ORACLE_FP32) && !defined(ORACLE_NAIVE)
+#define DIFF(a, b) ((real)(u[(a)] - u[(b)]))
+#else
+#define DIFF(a, b) (U(a) - U(b))
+#endif
 
 /* First derivative, centred, order p: antisymmetric pairs u_m - u_-m. */
 static real d1(const double *u, long s, real h, int p)
 {
     if (p == 4)
-        return (8 * (U(s) - U(-s)) - (U(2 * s) - U(-2 * s))) / (12 * h);
-    return (45 * (U(s) - U(-s)) - 9 * (U(2 * s) - U(-2 * s)) + (U(3 * s) - U(-3 * s))) / (60 * h);
+        return (8 * DIFF(s, -s) - DIFF(2 * s, -2 * s)) / (12 * h);
+    return (45 * DIFF(s, -s) - 9 * DIFF(2 * s, -2 * s) + DIFF(3 * s, -3 * s)) / (60 * h);
 }
 
 /* Lopsided first derivative, order p (the advection stencil of moving-
@@ -167,11 +182,10 @@ static real d1lop(const double *u, long s, real h, int p, int pos)
 {
     const long double *w = LOPW[p == 6];
     const int lo = -p / 2 + 1;
-    const real c = U(0);
     real acc = 0.0;
     for (int j = 0; j <= p; ++j) {
         const long o = pos ? (long)(lo + j) : -(long)(lo + j);
-        acc += (real)w[j] * (U(o * s) - c);   /* the weights sum to zero */
+        acc += (real)w[j] * DIFF(o * s, 0);   /* the weights sum to zero */
     }
     return (pos ? acc : -acc) / h;
 }
@@ -180,11 +194,10 @@ static real d1lop(const double *u, long s, real h, int p, int pos)
  * in differences from the centre value. */
 static real d2(const double *u, long s, real h, int p)
 {
-    const real c = U(0);
     if (p == 4)
-        return (16 * ((U(s) - c) + (U(-s) - c)) - ((U(2 * s) - c) + (U(-2 * s) - c))) / (12 * h * h);
-    return (270 * ((U(s) - c) + (U(-s) - c)) - 27 * ((U(2 * s) - c) + (U(-2 * s) - c))
-            + 2 * ((U(3 * s) - c) + (U(-3 * s) - c)))
+        return (16 * (DIFF(s, 0) + DIFF(-s, 0)) - (DIFF(2 * s, 0) + DIFF(-2 * s, 0))) / (12 * h * h);
+    return (270 * (DIFF(s, 0) + DIFF(-s, 0)) - 27 * (DIFF(2 * s, 0) + DIFF(-2 * s, 0))
+            + 2 * (DIFF(3 * s, 0) + DIFF(-3 * s, 0)))
            / (180 * h * h);
 }
 
@@ -218,11 +231,10 @@ static real binomial(int n, int k)
 static real ko1(const double *u, long s, real h, int p, real sigma)
 {
     const int r = p / 2 + 1;
-    const real c0 = U(0);
     real acc = 0;
     for (int m = 1; m <= r; ++m) {
         const real cm = (((m + r) & 1) ? -1 : 1) * binomial(2 * r, r + m);
-        acc += cm * ((U(m * s) - c0) + (U(-m * s) - c0));
+        acc += cm * (DIFF(m * s, 0) + DIFF(-m * s, 0));
     }
     const real sign = ((r + 1) & 1) ? -1.0 : 1.0;
     return sign * sigma / (ldexp(1.0, 2 * r) * h) * acc;

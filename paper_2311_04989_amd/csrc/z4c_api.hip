@@ -88,8 +88,11 @@ z4c_status check_params(const z4c_params *p)
     if (!(p->chi_floor > 0.0) || !(p->alpha_floor >= 0.0) || !std::isfinite(p->chi_floor)
         || !std::isfinite(p->alpha_floor))
         return fail(Z4C_EINVAL, "chi_floor must be > 0 and alpha_floor >= 0");
-    if (p->arith != Z4C_ARITH_FP64 && p->arith != Z4C_ARITH_FP32)
-        return fail(Z4C_EINVAL, "arith must be FP64 or FP32");
+    if (p->arith != Z4C_ARITH_FP64 && p->arith != Z4C_ARITH_FP32
+        && p->arith != Z4C_ARITH_FP32_NAIVE)
+        return fail(Z4C_EINVAL, "arith must be FP64, FP32 or FP32_NAIVE");
+    if (p->arith == Z4C_ARITH_FP32_NAIVE && p->fd_order != 6)
+        return fail(Z4C_ENOTSUP, "the naive FP32 form is built for order 6 only");
     if (p->advection != Z4C_ADVECT_CENTRED && p->advection != Z4C_ADVECT_LOPSIDED)
         return fail(Z4C_EINVAL, "advection must be CENTRED or LOPSIDED");
     if (p->advection == Z4C_ADVECT_LOPSIDED && p->arith != Z4C_ARITH_FP64)
@@ -381,6 +384,8 @@ z4c_status validate_stage(const z4c_plan *P, const double *u0_in, const double *
         return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
     if (!std::isfinite(dt))
         return fail(Z4C_EINVAL, "dt must be finite");
+    if (P->params.arith == Z4C_ARITH_FP32_NAIVE)
+        return fail(Z4C_ENOTSUP, "the naive FP32 form is a right-hand side only");
     if (c->read_u1 < 0 || c->read_u1 > 1 || c->write_u1 < 0 || c->write_u1 > 1)
         return fail(Z4C_EINVAL, "read_u1/write_u1 must be 0 or 1");
     return Z4C_OK;
@@ -1074,6 +1079,8 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
         return fail(Z4C_EINVAL, "autotune needs three distinct state buffers");
     if (reps < 1)
         return fail(Z4C_EINVAL, "reps must be >= 1");
+    if (P->params.arith == Z4C_ARITH_FP32_NAIVE)
+        return fail(Z4C_ENOTSUP, "the naive FP32 form is a right-hand side only (no autotuning)");
     z4c_status st = need_device(P);
     if (st != Z4C_OK)
         return st;

@@ -89,6 +89,9 @@ hipError_t launch_p4(int mode, int arith, int tx, int ty, int tz, int w, const S
 // Right-hand side / stage with lopsided advection (FP64, z4c_variants_lop.hip).
 hipError_t launch_lopsided(int mode, int fd_order, int tx, int ty, int tz, int w,
                            const StageArgs &a, hipStream_t s);
+// Naive-FP32 right-hand side (z4c_variants_naive.hip).
+hipError_t launch_naive(int fd_order, int tx, int ty, int tz, int w, const StageArgs &a,
+                        hipStream_t s);
 // Stage with the constraint monitor (FP64, z4c_variants_mon.hip).
 hipError_t launch_monitor(int fd_order, int tx, int ty, int tz, int w, const StageArgs &a,
                           hipStream_t s);

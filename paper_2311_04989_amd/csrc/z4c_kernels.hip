@@ -159,6 +159,9 @@ hipError_t launch_stage(int mode, int fd_order, int arith, int tx, int ty, int t
 {
     if (mode == MODE_RK_MON)
         return launch_monitor(fd_order, tx, ty, tz, waves, a, s);
+    if (arith == Z4C_ARITH_FP32_NAIVE && mode != MODE_CONS)
+        return mode == MODE_RHS ? launch_naive(fd_order, tx, ty, tz, waves, a, s)
+                                : hipErrorInvalidValue;
     if (fd_order == 4)
         return launch_p4(mode, arith, tx, ty, tz, waves, a, s);
     if (mode == MODE_CONS || arith != Z4C_ARITH_FP32)

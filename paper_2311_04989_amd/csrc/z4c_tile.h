@@ -639,6 +639,10 @@ struct LStager {
             }
         }
     }
+    // NAIVE: the values are rounded to float on their way into the tile, so
+    // that every stencil difference is one of float samples (the naive
+    // FP32 form, kept for precision comparisons).
+    template <bool NAIVE = false>
     __device__ __forceinline__ void store(double *lds, int t)
     {
 #pragma unroll
@@ -646,7 +650,7 @@ struct LStager {
             const int e = t + q * NT;
             if ((q + 1) * NT <= LVOL || e < LVOL) {
                 const int lx = e % LX, r1 = e / LX, ly = r1 % LY, lz = r1 / LY;
-                lds[lz * PXY + ly * PX + lx] = pf[q];
+                lds[lz * PXY + ly * PX + lx] = NAIVE ? double(float(pf[q])) : pf[q];
             }
         }
     }
@@ -1141,8 +1145,10 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
 // the constraint kernel does (same per-tile order).
 // LOP: lopsided stencils in the advection terms beta^k d_k u (re-read from
 // the staged field in LDS); every other derivative stays centred.
+// NAIVE (right-hand side, float arithmetic only): every staged value is
+// rounded to float before the stencil differences (the naive FP32 form).
 template <int P, int TX, int TY, int TZ, int WPE, typename R, int MODE, bool GEN, bool MON = false,
-          bool LOP = false>
+          bool LOP = false, bool NAIVE = false>
 __global__ void __launch_bounds__(TX *TY *TZ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 stage_kernel(const StageArgs a)
 {
@@ -1245,7 +1251,7 @@ stage_kernel(const StageArgs a)
             constexpr int FF = decltype(FC)::value;
             constexpr int NX = next_field<MODE>(FF);
             __syncthreads();
-            st.store(lds, t);
+            st.template store<NAIVE>(lds, t);
             if constexpr (NX >= 0)
                 st.prefetch(NX, t);
             const Old mine = pending;
@@ -1905,6 +1911,25 @@ hipError_t launch_variant(int mode, const StageArgs &a, hipStream_t s)
         else
             tile::stage_kernel<P, TX, TY, TZ, WPE, R, MODE_RK, false><<<grid, blk, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+// Right-hand side with the naive FP32 form (samples rounded to float before
+// the stencil differences).
+template <int P, int TX, int TY, int TZ, int WPE>
+hipError_t launch_variant_naive(const StageArgs &a, hipStream_t s)
+{
+    const int grid = grid_size(a);
+    if (grid <= 0)
+        return hipSuccess;
+    const dim3 blk(TX * TY * TZ);
+    const bool gen = a.halo == Z4C_GHOST_FROZEN || a.halo == Z4C_GHOST_NEIGHBOUR;
+    if (gen)
+        tile::stage_kernel<P, TX, TY, TZ, WPE, float, MODE_RHS, true, false, false, true>
+            <<<grid, blk, 0, s>>>(a);
+    else
+        tile::stage_kernel<P, TX, TY, TZ, WPE, float, MODE_RHS, false, false, false, true>
+            <<<grid, blk, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "libz4c.so")
 OK, EINVAL, ENOGHOST, EALIGN, EHIP, ENOTSUP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 LAPSE_1PLUSLOG, LAPSE_HARMONIC, LAPSE_FROZEN = 0, 1, 2
 SHIFT_GAMMADRIVER, SHIFT_FROZEN = 0, 1
-ARITH_FP64, ARITH_FP32 = 0, 1
+ARITH_FP64, ARITH_FP32, ARITH_FP32_NAIVE = 0, 1, 2
 ADVECT_CENTRED, ADVECT_LOPSIDED = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
