@@ -207,6 +207,18 @@ z4c_status z4c_rk_stage(z4c_plan *plan, const double *u0_in, double *u0_out, dou
 z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter,
                            double *cons, double *norms, void *stream);
 
+/* z4c_constraints for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results (bitwise), with the per-tile partial sums in
+ * a static device array of the library (8 MiB per device, held until the
+ * process ends) instead of the plan's buffer; the call allocates nothing.
+ * The plan itself (created beforehand) still owns its tables.  Plans of more
+ * than 65,536 tiles (z4c_plan_tiles) are refused with Z4C_ENOTSUP.  Every
+ * call on one device shares that array: calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller. */
+z4c_status z4c_constraints_noalloc(z4c_plan *plan, const double *u, const double *matter,
+                                   double *cons, double *norms, void *stream);
+
 /* z4c_rk_stage with the constraint monitor fused into the stage kernel (Sec.
  * 4.1 monitoring): the stage as z4c_rk_stage, and the constraints of its
  * input u0_in (the quantities and layouts of z4c_constraints) formed from

@@ -8,12 +8,17 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "z4c_internal.h"
 
 using namespace z4c;
+
+// Scratch of z4c_constraints_noalloc (partial sums, 16 doubles per tile).
+constexpr int NOALLOC_MAX_TILES = 65536;   // 8 MiB per device
+static __device__ __align__(256) double scratch[NOALLOC_MAX_TILES * 16];
 
 namespace {
 
@@ -586,6 +591,72 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
     return Z4C_OK;
 }
 
+z4c_status validate_constraints(const z4c_plan *P, const double *u, const double *matter,
+                                const double *cons, const double *norms)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!u || !norms)
+        return fail(Z4C_EINVAL, "u and norms must not be NULL");
+    if (cons == u || norms == u || (cons && cons == norms))
+        return fail(Z4C_EINVAL, "outputs must not alias u or each other");
+    if (!aligned8(u) || !aligned8(cons) || !aligned8(norms) || !aligned8(matter))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    if (!P->offsets32)
+        return fail(Z4C_ENOTSUP, "constraints need offset + 22*field_stride < 2^32 for every "
+                                 "block (32-bit element offsets from the state array base)");
+    return need_device(P);
+}
+
+// Constraint kernel + per-block norm reduction, with the per-tile partial
+// sums in `partial` (16 doubles per tile of the plan).
+z4c_status enqueue_constraints(z4c_plan *P, const double *u, const double *matter, double *cons,
+                               double *norms, double *partial, hipStream_t s)
+{
+    StageArgs a = base_args(P);
+    a.u = u;
+    a.matter = matter;
+    a.out = cons;
+    a.partial = partial;
+    z4c_status st = run_groups(P, MODE_CONS, Z4C_ARITH_FP64, a, s);
+    if (st != Z4C_OK)
+        return st;
+    const hipError_t e = launch_norm_reduce(P->blocks_d, P->nblocks, P->tile_start_d,
+                                            P->tile_count_d, partial, norms, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "norm reduction launch");
+    return Z4C_OK;
+}
+
+// Scratch of z4c_constraints_noalloc: the per-tile partial sums live in this
+// file-scope device array instead of the plan's buffer, so that the call
+// allocates nothing.  Each device holds its own copy; in host code the name
+// is only a stand-in, and the device address comes from hipGetSymbolAddress,
+// looked up once per device (at plan creation, or on the first call on that
+// device) and kept in noalloc_ptr.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+double *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex noalloc_mutex;
+
+// Device address of this device's scratch array (looked up on first use).
+z4c_status noalloc_scratch(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(Z4C_ENOTSUP, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(Z4C_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = noalloc_ptr[dev];
+    return Z4C_OK;
+}
+
 }  // namespace
 
 z4c_status z4c::set_error(z4c_status s, const char *msg) { return fail(s, msg); }
@@ -694,6 +765,12 @@ z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, in
         if (e != hipSuccess) {
             z4c_plan_destroy(P);
             return hip_fail(e, "plan device set-up");
+        }
+        double *scratch_d = nullptr;   // z4c_constraints_noalloc's scratch on this device
+        st = noalloc_scratch(&scratch_d);
+        if (st != Z4C_OK) {
+            z4c_plan_destroy(P);
+            return st;
         }
     }
     st = build_groups(P);
@@ -922,34 +999,31 @@ z4c_status z4c_rk_stage_monitor(z4c_plan *P, const double *u0_in, double *u0_out
 z4c_status z4c_constraints(z4c_plan *P, const double *u, const double *matter, double *cons,
                            double *norms, void *stream)
 {
-    if (!P)
-        return fail(Z4C_EINVAL, "plan is NULL");
-    if (!u || !norms)
-        return fail(Z4C_EINVAL, "u and norms must not be NULL");
-    if (cons == u || norms == u || (cons && cons == norms))
-        return fail(Z4C_EINVAL, "outputs must not alias u or each other");
-    if (!aligned8(u) || !aligned8(cons) || !aligned8(norms) || !aligned8(matter))
-        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
-    if (!P->offsets32)
-        return fail(Z4C_ENOTSUP, "constraints need offset + 22*field_stride < 2^32 for every "
-                                 "block (32-bit element offsets from the state array base)");
-    z4c_status st = need_device(P);
+    z4c_status st = validate_constraints(P, u, matter, cons, norms);
     if (st != Z4C_OK)
         return st;
-    StageArgs a = base_args(P);
-    a.u = u;
-    a.matter = matter;
-    a.out = cons;
-    a.partial = P->partial_d;
-    hipStream_t s = (hipStream_t)stream;
-    st = run_groups(P, MODE_CONS, Z4C_ARITH_FP64, a, s);
+    return enqueue_constraints(P, u, matter, cons, norms, P->partial_d, (hipStream_t)stream);
+}
+
+z4c_status z4c_constraints_noalloc(z4c_plan *P, const double *u, const double *matter,
+                                   double *cons, double *norms, void *stream)
+{
+    z4c_status st = validate_constraints(P, u, matter, cons, norms);
     if (st != Z4C_OK)
         return st;
-    const hipError_t e = launch_norm_reduce(P->blocks_d, P->nblocks, P->tile_start_d,
-                                            P->tile_count_d, P->partial_d, norms, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "norm reduction launch");
-    return Z4C_OK;
+    if (P->total_tiles > NOALLOC_MAX_TILES) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "z4c_constraints_noalloc: the plan has %lld tiles; the static scratch "
+                      "holds the partial sums of at most %d",
+                      P->total_tiles, NOALLOC_MAX_TILES);
+        return fail(Z4C_ENOTSUP, buf);
+    }
+    double *partial = nullptr;
+    st = noalloc_scratch(&partial);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_constraints(P, u, matter, cons, norms, partial, (hipStream_t)stream);
 }
 
 z4c_status z4c_ghost_fill(z4c_plan *P, int policy, double *u, const double *frozen, void *stream)

@@ -135,6 +135,7 @@ def lib():
         L.z4c_rk_stage.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
                                    ctypes.c_double, vp]
         L.z4c_constraints.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.z4c_constraints_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.z4c_rk_stage_monitor.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
                                            ctypes.c_double, vp, vp, vp]
         L.z4c_ghost_fill.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -175,7 +176,8 @@ def lib():
             getattr(L, name).restype = st
         for name in ("z4c_plan_create", "z4c_plan_destroy", "z4c_plan_set_params", "z4c_plan_set_halo",
                      "z4c_plan_set_neighbours", "z4c_plan_set_launch", "z4c_plan_get_launch",
-                     "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_ghost_fill", "z4c_rk_stage_monitor",
+                     "z4c_rhs", "z4c_rk_stage", "z4c_constraints", "z4c_constraints_noalloc",
+                     "z4c_ghost_fill", "z4c_rk_stage_monitor",
                      "z4c_step", "z4c_step_graph", "z4c_plan_autotune", "z4c_check_finite"):
             getattr(L, name).restype = st
         _lib = L
@@ -294,6 +296,11 @@ class Plan:
     def constraints(self, u, matter, cons, norms, stream=None):
         _check(lib().z4c_constraints(self._h, _ptr(u), _ptr(matter), _ptr(cons), _ptr(norms),
                                      _stream(stream)))
+
+    def constraints_noalloc(self, u, matter, cons, norms, stream=None):
+        """constraints with the library's static scratch (allocates nothing)."""
+        _check(lib().z4c_constraints_noalloc(self._h, _ptr(u), _ptr(matter), _ptr(cons),
+                                             _ptr(norms), _stream(stream)))
 
     def ghost_fill(self, policy, u, frozen=None, stream=None):
         _check(lib().z4c_ghost_fill(self._h, int(policy), _ptr(u), _ptr(frozen),
