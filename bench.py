@@ -33,6 +33,9 @@ FP64_PEAK_TFLOPS = 78.6
 # point per lane; an FMA counts two)
 FLOP_PER_PT_STAGE = 1844 + 882 + 2 * 1324 + 6
 FP32_PEAK_TFLOPS = 157.3
+# Relative L2 difference of the Hamiltonian constraint between the FP32 and the
+# FP64 runs of the precision study that the FP32 form must stay within.
+FP32_H_TOLERANCE = 1e-5
 # Algorithmic HBM bytes per interior point for each RK4 stage (22 FP64 fields,
 # each value moved once): stage 1 reads u0, writes u1 and u0'; stages 2-3 read
 # u0, u1, u2 and write u1, u0'; stage 4 reads u0, u1 and writes u0'.
@@ -62,6 +65,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-vs-FP64 constraint study on 8 x 128^3 blocks")
+    ap.add_argument("--precision-steps", type=int, default=100)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
@@ -264,6 +270,10 @@ def main():
         out["fp32"] = {"value": v32, "unit": "pt-stage/s", "ms_per_step": r32["ms"],
                        "speedup_vs_fp64": v32 / value,
                        "stage_kernel_ms": r32["stage_ms"].round(4).tolist()}
+        if not args.no_precision:
+            out["fp32"]["precision_study"] = precision_leg(args.precision_steps)
+            out["fp32"]["constraint_error"] = out["fp32"]["precision_study"]["constraint_error"]
+            out["fp32"]["constraint_tolerance"] = FP32_H_TOLERANCE
     if not args.no_batching:
         out["batching"] = batching(stream, args.steps)
     if not args.no_lopsided:
@@ -747,10 +757,59 @@ def cpu_baseline(bt, nsample):
     O.rk_step(sub, sub.u, dt=bt.dt)
     dt = time.time() - t0
     pts = sub.ninterior * 4
+    # one thread, on a sixteenth of the sample (the same share of every size)
+    idx1 = np.concatenate([rng.choice(np.nonzero(sizes == s)[0],
+                                      size=max(1, np.count_nonzero(sizes[idx] == s) // 16),
+                                      replace=False) for s in (8, 16, 24, 32)])
+    sub1 = bt.subset(idx1)
+    O.ghost_fill(sub1, sub1.u)
+    t1 = time.time()
+    O.rk_step(sub1, sub1.u, dt=bt.dt, nthreads=1)
+    dt1 = time.time() - t1
+    host = host_info()
     return {"value": pts / dt, "unit": "pt-stage/s", "cores": O.max_threads(), "kind": "oracle",
+            "cpu_model": host["cpu_model"], "nproc": host["nproc"],
+            "value_1thread": sub1.ninterior * 4 / dt1,
             "sample": f"one RK4 step (4 stages + periodic ghost refresh) of {len(idx)} of the "
                       f"{len(bt.blocks)} blocks ({sub.ninterior} interior points) of the same "
-                      f"level set, {dt:.1f} s"}
+                      f"level set, {dt:.1f} s on all threads; 1 thread: {len(idx1)} blocks "
+                      f"({sub1.ninterior} interior points), {dt1:.1f} s"}
+
+
+def precision_leg(steps):
+    """The FP32 form against FP64 on the precision-study level set (8 blocks
+    of 128^3, star metric with matter and 1e-6 noise, neighbour and frozen
+    ghosts): `steps` RK4 steps of each; the relative L2 difference of their
+    Hamiltonian-constraint fields at the end, against the stated tolerance."""
+    import torch
+
+    from paper_2311_04989_amd import precision_study as PS
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    bt = W.config5()
+    log(f"[bench] precision study level set generated in {time.time() - t0:.1f}s")
+    every = max(1, steps // 4)
+    r64, _, h64 = PS.evolve(bt, Z.ARITH_FP64, steps, every, stream)
+    r32, _, _ = PS.evolve(bt, Z.ARITH_FP32, steps, every, stream, h_ref=h64)
+    del h64
+    end32, end64 = r32["history"][-1], r64["history"][-1]
+    err = end32["dH_L2"] / end64["H_L2"]
+    return {"workload": "8 MeshBlocks 128^3 + 4 ghosts tiling [-16,16]^3, star metric + matter "
+                        "blobs + 1e-6 noise, neighbour + frozen outer ghosts, 6th-order FD, "
+                        f"KO 0.5, {steps} RK4 steps of dt = dx/4, FP32 arithmetic vs FP64",
+            "steps": steps,
+            "constraint_error": err,
+            "constraint_error_def": "||H_fp32 - H_fp64||_2 / ||H_fp64||_2 after the last step",
+            "tolerance": FP32_H_TOLERANCE,
+            "within_tolerance": bool(err <= FP32_H_TOLERANCE),
+            "H_L2_fp64": [r64["history"][0]["H_L2"], end64["H_L2"]],
+            "H_L2_fp32": [r32["history"][0]["H_L2"], end32["H_L2"]],
+            "fp64_ms_per_step": r64["ms_per_step"], "fp32_ms_per_step": r32["ms_per_step"],
+            "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
+            "nonfinite": [r64["nonfinite"], r32["nonfinite"]]}
 
 
 if __name__ == "__main__":
