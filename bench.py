@@ -141,7 +141,10 @@ def main():
         regs = [y0.clone(), y0.clone(), y0.clone(), torch.zeros_like(y0)]
         plan.ghost_fill(Z.GHOST_PERIODIC, regs[0], stream=stream)
         plan.set_halo(Z.GHOST_PERIODIC)   # stage launches outside the step read the same way
+        default_ms = None
         if not args.no_autotune:
+            if label == "fp64":
+                default_ms = step_time(plan, regs, bt, stream, args.warmup, args.steps)
             plan.autotune(regs[0], regs[1], regs[3], None, reps=3, stream=stream)
         launches = {s: plan.get_launch(s, s, s) for s in (8, 16, 24, 32)}
         torch.cuda.synchronize()
@@ -188,8 +191,24 @@ def main():
         torch.cuda.synchronize()
         ghost_ms = e0.elapsed_time(e1)
         nonfinite = plan.check_finite(regs[0], stream=stream)
+        queue = None
+        if label == "fp64" and not args.no_autotune:
+            # the tuned shapes once more as persistent work-queue launches
+            ncu = torch.cuda.get_device_properties(0).multi_processor_count
+            grid_l = {n: plan.get_launch(n, n, n) for n in (8, 16, 24, 32)}
+            timings = {}
+            for mode in ("grid", "persistent"):
+                for n, (tile, pers, waves) in grid_l.items():
+                    plan.set_launch(n, n, n, tile, 0 if mode == "grid" else ncu, waves)
+                timings[mode] = stage2_time(plan, regs, bt, stream, reps)
+            for n, (tile, pers, waves) in grid_l.items():
+                plan.set_launch(n, n, n, tile, pers, waves)
+            queue = {"grid_stage2_ms": timings["grid"], "persistent_stage2_ms": timings["persistent"],
+                     "persistent_workgroups": ncu,
+                     "persistent_le_grid": bool(timings["persistent"] <= 1.01 * timings["grid"])}
         results[label] = dict(ms=ms, stage_ms=stage_ms, ghost_ms=ghost_ms, launches=launches,
-                              nonfinite=nonfinite, monitor=mon)
+                              nonfinite=nonfinite, monitor=mon, default_ms=default_ms,
+                              queue=queue)
         log(f"[bench] {label}: stage kernels {np.round(stage_ms, 3).tolist()} ms, "
             f"(a separate ghost refresh would cost {ghost_ms:.3f} ms), non-finite values "
             f"{nonfinite}")
@@ -261,6 +280,11 @@ def main():
         },
         "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
         "hbm_copy_gbs": copy_gbs,
+        "autotune": None if r64["default_ms"] is None else {
+            "default_launch": "8x8x8 tiles, two waves per SIMD, grid launch (the plan's default)",
+            "default_ms_per_step": r64["default_ms"], "tuned_ms_per_step": r64["ms"],
+            "tuned_ge_default": bool(r64["ms"] <= r64["default_ms"]),
+            "persistent_vs_grid": r64["queue"]},
         "fp64_flop_per_pt_stage": FLOP_PER_PT_STAGE,
         "fp64_alu_frac": value * FLOP_PER_PT_STAGE / (FP64_PEAK_TFLOPS * 1e12),
     }
@@ -286,6 +310,49 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bt, args.cpu_sample_blocks)
     print(json.dumps(out), flush=True)
+
+
+def step_time(plan, regs, bt, stream, warmup, steps):
+    """ms per RK4 step of `plan` (graph replay), on copies of the registers."""
+    import torch
+
+    from paper_2311_04989_amd import z4c as Z
+
+    r = [x.clone() for x in regs]
+    for _ in range(max(1, warmup)):
+        plan.step(r, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream,
+                  flags=Z.STEP_NO_FINAL_FILL)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.step(r, None, Z.RK4, bt.dt, Z.GHOST_PERIODIC, graph=True, stream=stream,
+                  flags=Z.STEP_NO_FINAL_FILL)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del r
+    return e0.elapsed_time(e1) / steps
+
+
+def stage2_time(plan, regs, bt, stream, reps):
+    """Median ms of an RK4 stage-2 launch of `plan`."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import z4c as Z
+
+    out = torch.empty_like(regs[0])
+    plan.rk_stage(regs[1], out, regs[3], regs[0], None, Z.RK4[1], bt.dt, stream=stream)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.rk_stage(regs[1], out, regs[3], regs[0], None, Z.RK4[1], bt.dt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del out
+    return float(np.median(ms))
 
 
 def lopsided_timing(bt, stream, reps, centred_ms):
@@ -442,13 +509,27 @@ def batching(stream, reps):
            "interior_points": n_int}
     log("[bench] batching: 512 per-block launches")
     res["per_block_launches_ms"] = timed(per_block)
-    plan.set_launch(16, 16, 16, (8, 8, 8), 0, 2)
-    res["grid_launch_ms"] = timed(whole)
-    nper = 2 * torch.cuda.get_device_properties(0).multi_processor_count
-    plan.set_launch(16, 16, 16, (8, 8, 8), nper, 2)
-    res["persistent_launch_ms"] = timed(whole)
-    res["persistent_workgroups"] = nper
-    res["note"] = "(median, min) over the timed repetitions, ms per stage"
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    # every launch shape as a grid launch and as a persistent (work-queue)
+    # launch of one and two workgroups per CU
+    shapes = {}
+    for tile, waves in (((8, 8, 8), 2), ((8, 8, 4), 2), ((8, 8, 4), 1), ((8, 4, 8), 1)):
+        row = {}
+        for pers in (0, ncu, 2 * ncu):
+            plan.set_launch(16, 16, 16, tile, pers, waves)
+            row["grid" if pers == 0 else f"persistent_{pers}"] = timed(whole)
+        shapes["x".join(map(str, tile)) + f"_w{waves}"] = row
+    best_key = min(shapes, key=lambda k: shapes[k]["grid"][0])
+    best = shapes[best_key]
+    pers_best = min((v for k, v in best.items() if k != "grid"), key=lambda v: v[0])
+    res["launch_shapes_ms"] = shapes
+    res["grid_launch_ms"] = best["grid"]
+    res["persistent_launch_ms"] = pers_best
+    res["best_shape"] = best_key
+    res["persistent_le_grid"] = bool(pers_best[0] <= best["grid"][0] * 1.01)
+    res["note"] = ("(median, min) over the timed repetitions, ms per stage; grid and "
+                   "persistent compared in the shape whose grid launch is fastest; "
+                   "persistent_le_grid allows 1 % timing noise")
     res["pt_stage_per_s"] = {k[:-3]: n_int / (res[k][0] * 1e-3)
                              for k in ("per_block_launches_ms", "grid_launch_ms",
                                        "persistent_launch_ms")}
@@ -753,6 +834,7 @@ def cpu_baseline(bt, nsample):
                               for s in (8, 16, 24, 32)])
     sub = bt.subset(idx)
     O.ghost_fill(sub, sub.u)
+    cores = O.max_threads()
     t0 = time.time()
     O.rk_step(sub, sub.u, dt=bt.dt)
     dt = time.time() - t0
@@ -767,7 +849,7 @@ def cpu_baseline(bt, nsample):
     O.rk_step(sub1, sub1.u, dt=bt.dt, nthreads=1)
     dt1 = time.time() - t1
     host = host_info()
-    return {"value": pts / dt, "unit": "pt-stage/s", "cores": O.max_threads(), "kind": "oracle",
+    return {"value": pts / dt, "unit": "pt-stage/s", "cores": cores, "kind": "oracle",
             "cpu_model": host["cpu_model"], "nproc": host["nproc"],
             "value_1thread": sub1.ninterior * 4 / dt1,
             "sample": f"one RK4 step (4 stages + periodic ghost refresh) of {len(idx)} of the "

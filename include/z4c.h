@@ -160,10 +160,11 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *plan, const int *neighbours);
 /* Launch shape for the blocks of one size class (nx, ny, nz) (0 = all).
  * tile_x/y/z: interior points per workgroup, one thread per point;
  * persistent: 0 = one workgroup per tile, otherwise that many workgroups
- * each take a contiguous run of tiles; waves: occupancy the kernel variant
- * is compiled for, in waves per SIMD (0 = 2; its register budget is
- * 512/waves per lane).  Supported: 8x8x8 and 8x8x4 with waves 2, and for
- * order 6 also 8x8x4 with waves 1. */
+ * taking tiles from a work queue (per-XCD ranges of consecutive tiles, then
+ * the other ranges' leftovers); waves: occupancy the kernel variant is
+ * compiled for, in waves per SIMD (0 = 2; its register budget is 512/waves
+ * per lane).  Supported: 8x8x8 and 8x8x4 with waves 2, and for order 6 also
+ * 8x8x4 and 8x4x8 with waves 1. */
 typedef struct {
     int tile_x, tile_y, tile_z;
     int persistent;
@@ -281,10 +282,21 @@ z4c_status z4c_step_graph(z4c_plan *plan, const z4c_step_desc *desc, int *result
 
 /* Time each supported launch shape per size class on the caller's buffers
  * (u0 read, u0_out/u1 overwritten at interior points, one RK4-like stage)
- * and keep the fastest; `reps` timed launches per candidate.  Results are
- * readable with z4c_plan_get_launch.  Synchronises the stream. */
+ * and keep the fastest; `reps` timed launches per candidate.  Candidates:
+ * every supported tile shape and occupancy, each as a grid launch and as
+ * persistent launches of one and two workgroups per CU.  With a tuning
+ * cache set (z4c_set_tune_cache), size classes found there under the same
+ * key (device architecture, order, arithmetic, advection, halo rule, block
+ * interior size, ghosts) take the stored shape without timing, and newly
+ * timed ones are added to it.  Results are readable with
+ * z4c_plan_get_launch.  Synchronises the stream. */
 z4c_status z4c_plan_autotune(z4c_plan *plan, const double *u0, double *u0_out, double *u1,
                              const double *matter, int reps, void *stream);
+
+/* Path of the autotuning cache file used by z4c_plan_autotune (process-wide;
+ * NULL or "" = no cache).  One text line per entry; written atomically
+ * (temporary file + rename) after a tuning run that timed new classes. */
+z4c_status z4c_set_tune_cache(const char *path);
 
 /* Scan the interior of u for non-finite values; *flag = count found (host
  * int, the call synchronises the stream). */

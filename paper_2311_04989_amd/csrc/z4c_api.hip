@@ -47,6 +47,7 @@ struct LaunchGroup {
     int tx, ty, tz, persistent, waves;
     std::vector<Tile> tiles;
     Tile *tiles_d = nullptr;
+    int *queue_d = nullptr;   // persistent launches: 8 tile counters
     long long tile_base = 0;
 };
 
@@ -193,9 +194,12 @@ struct z4c_plan {
 
     void free_groups()
     {
-        for (auto &g : groups)
+        for (auto &g : groups) {
             if (g.tiles_d)
                 (void)hipFree(g.tiles_d);
+            if (g.queue_d)
+                (void)hipFree(g.queue_d);
+        }
         groups.clear();
         if (tile_start_d)
             (void)hipFree(tile_start_d);
@@ -300,6 +304,8 @@ z4c_status build_groups(z4c_plan *P)
     for (auto &g : P->groups) {
         HIP_TRY(hipMalloc(&g.tiles_d, sizeof(Tile) * std::max<size_t>(1, g.tiles.size())),
                 "hipMalloc(tiles)");
+        if (g.persistent)
+            HIP_TRY(hipMalloc(&g.queue_d, sizeof(int) * 16), "hipMalloc(queue)");
         HIP_TRY(hipMemcpy(g.tiles_d, g.tiles.data(), sizeof(Tile) * g.tiles.size(),
                           hipMemcpyHostToDevice),
                 "hipMemcpy(tiles)");
@@ -344,7 +350,13 @@ z4c_status run_groups(z4c_plan *P, int mode, int arith, StageArgs a, hipStream_t
         a.tiles = g.tiles_d;
         a.ntiles = (int)g.tiles.size();
         a.persistent = g.persistent;
+        a.queue = g.queue_d;
         a.tile_base = g.tile_base;
+        if (g.persistent && !g.tiles.empty()) {
+            const hipError_t ez = launch_zero_queue(g.queue_d, s);
+            if (ez != hipSuccess)
+                return hip_fail(ez, "tile-queue reset launch");
+        }
         const bool lop = P->params.advection == Z4C_ADVECT_LOPSIDED
                       && (mode == MODE_RHS || mode == MODE_RK);
         const hipError_t e = lop ? launch_lopsided(mode, P->params.fd_order, g.tx, g.ty, g.tz,
@@ -626,6 +638,84 @@ z4c_status enqueue_constraints(z4c_plan *P, const double *u, const double *matte
     if (e != hipSuccess)
         return hip_fail(e, "norm reduction launch");
     return Z4C_OK;
+}
+
+// Autotuning cache: one line per size class and scheme,
+//   <key> <tile_x> <tile_y> <tile_z> <persistent> <waves> <ms per launch>
+// keyed by the device architecture, order, arithmetic, advection, halo rule
+// and the block's interior and ghost sizes.  The path is set with
+// z4c_set_tune_cache (empty: no cache).
+struct TuneEntry {
+    z4c_launch launch;
+    float ms;
+};
+struct TuneCache {
+    std::map<std::string, TuneEntry> entries;
+};
+std::mutex g_tune_mutex;
+std::string g_tune_path;
+
+std::string tune_key(const z4c_plan *P, const SizeClass &c)
+{
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');   // drop feature suffixes
+        if (colon != std::string::npos)
+            arch.resize(colon);
+    }
+    const z4c_block &B = P->blocks[c.blocks.front()];
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "%s:p%d:arith%d:adv%d:halo%d:n%dx%dx%d:ng%d", arch.c_str(),
+                  P->params.fd_order, P->params.arith, P->params.advection, P->halo, c.nx, c.ny,
+                  c.nz, B.ng);
+    return buf;
+}
+
+TuneCache tune_cache_load()
+{
+    TuneCache c;
+    std::string path;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        path = g_tune_path;
+    }
+    if (path.empty())
+        return c;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f)
+        return c;
+    char key[192];
+    z4c_launch L{};
+    float ms = 0.f;
+    while (std::fscanf(f, "%191s %d %d %d %d %d %f", key, &L.tile_x, &L.tile_y, &L.tile_z,
+                       &L.persistent, &L.waves, &ms) == 7)
+        c.entries[key] = TuneEntry{L, ms};
+    std::fclose(f);
+    return c;
+}
+
+void tune_cache_store(const TuneCache &c)
+{
+    std::string path;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        path = g_tune_path;
+    }
+    if (path.empty())
+        return;
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f)
+        return;
+    for (const auto &e : c.entries)
+        std::fprintf(f, "%s %d %d %d %d %d %.6f\n", e.first.c_str(), e.second.launch.tile_x,
+                     e.second.launch.tile_y, e.second.launch.tile_z, e.second.launch.persistent,
+                     e.second.launch.waves, e.second.ms);
+    std::fclose(f);
+    (void)std::rename(tmp.c_str(), path.c_str());
 }
 
 // Scratch of z4c_constraints_noalloc: the per-tile partial sums live in this
@@ -1160,20 +1250,35 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
         return st;
     hipStream_t s = (hipStream_t)stream;
     const z4c_rk_coeffs c{0.0, 1.0 / 3.0, 0.0, 0.0, 1.0, 0.5, 1, 1};
-    // earlier candidates win near-ties: a later one must be 5 % faster
-    static const int shapes[][4] = {{8, 8, 4, 1}, {8, 8, 8, 2}, {8, 8, 4, 2}};
+    // Candidates: every supported tile shape and occupancy, as a grid launch
+    // and as persistent launches of one or two workgroups per CU; earlier
+    // candidates win near-ties (a later one must be 5 % faster).
+    static const int shapes[][4] = {{8, 8, 4, 1}, {8, 4, 8, 1}, {8, 8, 8, 2}, {8, 8, 4, 2}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     const std::vector<SizeClass> saved = P->classes;
     std::vector<z4c_launch> best(P->classes.size());
+    std::vector<float> best_time(P->classes.size(), 0.f);
+    TuneCache cache = tune_cache_load();
+    std::vector<std::string> keys(saved.size());
     for (size_t ci = 0; ci < saved.size(); ++ci) {
+        keys[ci] = tune_key(P, saved[ci]);
+        auto hit = cache.entries.find(keys[ci]);
+        if (hit != cache.entries.end()
+            && stage_shape_supported(P->params.fd_order, hit->second.launch.tile_x,
+                                     hit->second.launch.tile_y, hit->second.launch.tile_z,
+                                     hit->second.launch.waves)) {
+            best[ci] = hit->second.launch;
+            best_time[ci] = -1.f;   // from the cache
+            continue;
+        }
         float best_ms = 1e30f;
         for (const auto &sh : shapes) {
             if (!stage_shape_supported(P->params.fd_order, sh[0], sh[1], sh[2], sh[3]))
                 continue;
-            for (int pers : {0, 1}) {
-                z4c_launch L{sh[0], sh[1], sh[2], pers ? 2 * P->num_cus : 0, sh[3]};
+            for (int pers : {0, 1, 2}) {
+                z4c_launch L{sh[0], sh[1], sh[2], pers * P->num_cus, sh[3]};
                 // a plan view holding only this size class
                 P->classes.assign(1, saved[ci]);
                 P->classes[0].launch = L;
@@ -1193,6 +1298,7 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
                 if (st == Z4C_OK && ms < 0.95f * best_ms) {
                     best_ms = ms;
                     best[ci] = L;
+                    best_time[ci] = ms / reps;
                 }
             }
             if (st != Z4C_OK)
@@ -1204,11 +1310,27 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     P->classes = saved;
-    if (st == Z4C_OK)
-        for (size_t ci = 0; ci < saved.size(); ++ci)
+    if (st == Z4C_OK) {
+        bool fresh = false;
+        for (size_t ci = 0; ci < saved.size(); ++ci) {
             P->classes[ci].launch = best[ci];
+            if (best_time[ci] >= 0.f) {
+                cache.entries[keys[ci]] = TuneEntry{best[ci], best_time[ci]};
+                fresh = true;
+            }
+        }
+        if (fresh)
+            tune_cache_store(cache);
+    }
     const z4c_status st2 = build_groups(P);
     return st != Z4C_OK ? st : st2;
+}
+
+z4c_status z4c_set_tune_cache(const char *path)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_path = path ? std::string(path) : std::string();
+    return Z4C_OK;
 }
 
 z4c_status z4c_check_finite(z4c_plan *P, const double *u, long long *count, void *stream)

@@ -34,7 +34,8 @@ struct StageArgs {
     const float *fac32;      // the same factors rounded to float
     const Tile *tiles;
     int ntiles;
-    int persistent;          // 0: one workgroup per tile
+    int persistent;          // 0: one workgroup per tile; else that many workgroups
+    int *queue;              // persistent: 8 tile counters (one per XCD range), zeroed
     long long tile_base;     // global index of tiles[0] (norm partial sums)
     const double *u;         // input state (u0 for a stage)
     const double *matter;    // nullptr = vacuum
@@ -103,6 +104,9 @@ hipError_t launch_finite_count(const z4c_block *blocks, int nblocks, const long 
                                long long total_pts, const double *u,
                                unsigned long long *count, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+// Zero the 8 tile counters of a persistent launch (a kernel, so that captured
+// graphs replay it).
+hipError_t launch_zero_queue(int *q, hipStream_t s);
 
 // Read access to a plan from other translation units: its host block table,
 // its device copy (nullptr without a device).

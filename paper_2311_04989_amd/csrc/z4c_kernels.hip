@@ -143,14 +143,22 @@ __global__ void finite_count_kernel(const z4c_block *blocks, int nblocks, const 
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
 
+__global__ void zero_queue_kernel(int *q)
+{
+    if (threadIdx.x < 8)
+        q[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 bool stage_shape_supported(int fd_order, int tx, int ty, int tz, int waves)
 {
+    // one wave per SIMD (a 256-register budget plus as many accumulation
+    // registers): 256-point tiles 8x8x4 and 8x4x8 of the order-6 kernels
+    if (tx == 8 && ty == 4 && tz == 8)
+        return waves == 1 && fd_order == 6;
     if (tx != 8 || ty != 8 || (tz != 8 && tz != 4))
         return false;
-    // one wave per SIMD (a 256-register budget plus as many accumulation
-    // registers) for 8x8x4 tiles of the order-6 kernels
     return waves == 2 || (waves == 1 && tz == 4 && fd_order == 6);
 }
 
@@ -197,6 +205,12 @@ hipError_t launch_finite_count(const z4c_block *blocks, int nblocks, const long 
     const long long nb = (total_pts + 255) / 256;
     finite_count_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(blocks, nblocks, pt_start,
                                                                 total_pts, u, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_queue(int *q, hipStream_t s)
+{
+    zero_queue_kernel<<<1, 64, 0, s>>>(q);
     return hipGetLastError();
 }
 

@@ -387,6 +387,52 @@ __device__ __forceinline__ int xcd_logical(int w, int G)
     return x * q + (x < r ? x : r) + k;
 }
 
+// Work distribution of a tile launch.  Grid launch (a.persistent == 0): one
+// workgroup per tile, workgroup w taking the tile of logical index
+// xcd_logical(w), so that consecutive tiles (neighbours in one block, which
+// share halo points) run on one XCD and meet in its L2.  Persistent launch: the
+// tiles are cut into 8 contiguous ranges, one per XCD; a workgroup takes the
+// next tile of its XCD's range from that range's counter in a.queue (zeroed
+// before the launch), and once the range is exhausted the next tiles of the
+// other ranges in turn, so that no XCD idles while another has tiles left.
+// Every workgroup ends when all counters are exhausted.
+__device__ __forceinline__ int grab_tile(const StageArgs &a)
+{
+    const int x0 = blockIdx.x & 7;
+    for (int d = 0; d < 8; ++d) {
+        const int x = (x0 + d) & 7;
+        const int lo = (int)(((long long)x * a.ntiles) >> 3);
+        const int hi = (int)(((long long)(x + 1) * a.ntiles) >> 3);
+        if (lo >= hi)
+            continue;
+        const int k = atomicAdd(a.queue + x, 1);
+        if (k < hi - lo)
+            return lo + k;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int first_tile(const StageArgs &a, int t, int *slot)
+{
+    if (!a.persistent)
+        return xcd_logical(blockIdx.x, gridDim.x);
+    if (t == 0)
+        *slot = grab_tile(a);
+    __syncthreads();
+    return *slot;
+}
+
+// Called by every thread after the tile's closing barrier.
+__device__ __forceinline__ int next_tile(const StageArgs &a, int t, int *slot)
+{
+    if (!a.persistent)
+        return -1;
+    if (t == 0)
+        *slot = grab_tile(a);
+    __syncthreads();
+    return *slot;
+}
+
 // Algebraic enforcement after a stage (double): det(gt) = 1, tr(At) = 0, floors.
 __device__ __forceinline__ void enforce(double v[NFIELD], double chi_floor, double alpha_floor)
 {
@@ -731,12 +777,8 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
     const int tx = t % TX, ty = (t / TX) % TY, tz = t / (TX * TY);
     const double *lc = lds + (tz + RAD) * PXY + (ty + RAD) * PX + (tx + RAD);
 
-    const int G = gridDim.x;
-    const int L = xcd_logical(blockIdx.x, G);
-    const int tbeg = a.persistent ? (int)(((long long)L * a.ntiles) / G) : L;
-    const int tend = a.persistent ? (int)(((long long)(L + 1) * a.ntiles) / G) : L + 1;
-
-    for (int tile = tbeg; tile < tend; ++tile) {
+    __shared__ int tile_slot;
+    for (int tile = first_tile(a, t, &tile_slot); tile >= 0; tile = next_tile(a, t, &tile_slot)) {
         const Tile T = a.tiles[tile];
         const z4c_block B = a.blocks[T.block];
         const int ng = B.ng;
@@ -1203,12 +1245,8 @@ stage_kernel(const StageArgs a)
     const int tofs = tz * PXY + ty * PX + tx + CO;
     int loff = tofs;
 
-    const int G = gridDim.x;
-    const int L = xcd_logical(blockIdx.x, G);
-    const int tbeg = a.persistent ? (int)(((long long)L * a.ntiles) / G) : L;
-    const int tend = a.persistent ? (int)(((long long)(L + 1) * a.ntiles) / G) : L + 1;
-
-    for (int tile = tbeg; tile < tend; ++tile) {
+    __shared__ int tile_slot;
+    for (int tile = first_tile(a, t, &tile_slot); tile >= 0; tile = next_tile(a, t, &tile_slot)) {
         const Tile T = a.tiles[tile];
         const z4c_block B = a.blocks[T.block];
         const int ng = B.ng;

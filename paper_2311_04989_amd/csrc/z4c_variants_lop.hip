@@ -14,6 +14,8 @@ hipError_t launch_lopsided(int mode, int fd_order, int tx, int ty, int tz, int w
             return launch_variant_lop<6, 8, 8, 4, 2>(mode, a, s);
         if (tx == 8 && ty == 8 && tz == 4 && w == 1)
             return launch_variant_lop<6, 8, 8, 4, 1>(mode, a, s);
+        if (tx == 8 && ty == 4 && tz == 8 && w == 1)
+            return launch_variant_lop<6, 8, 4, 8, 1>(mode, a, s);
     } else if (fd_order == 4) {
         if (tx == 8 && ty == 8 && tz == 8 && w == 2)
             return launch_variant_lop<4, 8, 8, 8, 2>(mode, a, s);

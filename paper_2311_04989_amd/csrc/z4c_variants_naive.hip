@@ -16,6 +16,8 @@ hipError_t launch_naive(int fd_order, int tx, int ty, int tz, int w, const Stage
         return launch_variant_naive<6, 8, 8, 4, 2>(a, s);
     if (tx == 8 && ty == 8 && tz == 4 && w == 1)
         return launch_variant_naive<6, 8, 8, 4, 1>(a, s);
+    if (tx == 8 && ty == 4 && tz == 8 && w == 1)
+        return launch_variant_naive<6, 8, 4, 8, 1>(a, s);
     return hipErrorInvalidValue;
 }
 

@@ -12,6 +12,8 @@ hipError_t launch_p6_f32(int mode, int tx, int ty, int tz, int w, const StageArg
         return launch_variant<6, 8, 8, 4, 2, float>(mode, a, s);
     if (tx == 8 && ty == 8 && tz == 4 && w == 1)
         return launch_variant<6, 8, 8, 4, 1, float>(mode, a, s);
+    if (tx == 8 && ty == 4 && tz == 8 && w == 1)
+        return launch_variant<6, 8, 4, 8, 1, float>(mode, a, s);
     return hipErrorInvalidValue;
 }
 

@@ -7,6 +7,8 @@ hipError_t launch_p6_f64(int mode, int tx, int ty, int tz, int w, const StageArg
                          hipStream_t s)
 {
     if (mode == MODE_CONS) {
+        if (ty == 4)
+            return launch_cons<6, 8, 4, 8>(a, s);
         if (tz == 4)
             return launch_cons<6, 8, 8, 4>(a, s);
         return launch_cons<6, 8, 8, 8>(a, s);
@@ -17,6 +19,8 @@ hipError_t launch_p6_f64(int mode, int tx, int ty, int tz, int w, const StageArg
         return launch_variant<6, 8, 8, 4, 2, double>(mode, a, s);
     if (tx == 8 && ty == 8 && tz == 4 && w == 1)
         return launch_variant<6, 8, 8, 4, 1, double>(mode, a, s);
+    if (tx == 8 && ty == 4 && tz == 8 && w == 1)
+        return launch_variant<6, 8, 4, 8, 1, double>(mode, a, s);
     return hipErrorInvalidValue;
 }
 

@@ -143,6 +143,8 @@ def lib():
         L.z4c_step_graph.argtypes = [vp, ctypes.POINTER(StepDesc), ctypes.POINTER(ctypes.c_int),
                                      vp]
         L.z4c_plan_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
+        L.z4c_set_tune_cache.argtypes = [ctypes.c_char_p]
+        L.z4c_set_tune_cache.restype = st
         L.z4c_check_finite.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]
         L.z4c_strerror.argtypes = [st]
         L.z4c_strerror.restype = ctypes.c_char_p
@@ -182,6 +184,11 @@ def lib():
             getattr(L, name).restype = st
         _lib = L
     return _lib
+
+
+def set_tune_cache(path):
+    """Autotuning cache file of the process (None: no cache)."""
+    _check(lib().z4c_set_tune_cache(None if path is None else str(path).encode()))
 
 
 def _check(status: int):

@@ -193,16 +193,17 @@ def _launch_plan(bt, arith, tile, pers, waves):
 
 def test_launch_shape_and_persistence_do_not_change_results():
     """Within one kernel family (the same per-point arithmetic) results are
-    bitwise independent of tile shape, persistence and tile order: two
-    waves per SIMD (8x8x8 and 8x8x4 tiles), and one wave per SIMD (8x8x4,
-    mixed derivatives in two passes, compared with the oracle in
-    test_one_wave_variant_parity)."""
+    bitwise independent of tile shape, persistence (work-queue order) and
+    tile order: two waves per SIMD (8x8x8 and 8x8x4 tiles), and one wave per
+    SIMD (8x8x4 and 8x4x8, mixed derivatives in two passes, compared with the
+    oracle in test_one_wave_variant_parity)."""
     Z = z4c()
     bt = W.random_batch(11, nblocks=4, nmax=30, fd_order=6)
     note("launch-shape invariance")
     families = {2: [((8, 8, 8), 0), ((8, 8, 4), 0), ((8, 8, 8), 7), ((8, 8, 4), 3),
                     ((8, 8, 8), 1), ((8, 8, 4), 1000)],
-                1: [((8, 8, 4), 0), ((8, 8, 4), 5), ((8, 8, 4), 1), ((8, 8, 4), 1000)]}
+                1: [((8, 8, 4), 0), ((8, 8, 4), 5), ((8, 8, 4), 1), ((8, 8, 4), 1000),
+                    ((8, 4, 8), 0), ((8, 4, 8), 3), ((8, 4, 8), 256)]}
     for waves, shapes in families.items():
         for arith in (Z.ARITH_FP64, Z.ARITH_FP32):
             ref = stage_ref = None
@@ -228,6 +229,8 @@ def test_one_wave_variant_parity(seed):
     g = gpu_rhs(bt, plan=_launch_plan(bt, Z.ARITH_FP64, (8, 8, 4), 0, 1))
     rows = compare(bt, g, O.rhs(bt), O.rhs(bt, ext=True))
     assert_parity(rows, f"one-wave {seed} rhs\n" + report(rows))
+    g2 = gpu_rhs(bt, plan=_launch_plan(bt, Z.ARITH_FP64, (8, 4, 8), 7, 1))
+    assert np.array_equal(g2, g)
     gout, _ = gpu_stage(bt, Z.RK4[1], 0.01, u1_init=bt.u,
                         plan=_launch_plan(bt, Z.ARITH_FP64, (8, 8, 4), 3, 1))
     o64 = bt.u.copy()
@@ -413,3 +416,32 @@ def test_check_finite_counts_bad_points():
     bt.view(u, 0, 2)[0, 0, 0] = np.nan     # a ghost point: not counted
     plan = Z.plan_for(bt)
     assert plan.check_finite(dev(u)) == 2
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The autotuner stores the shape it picked per size class in the cache
+    file, and a second plan of the same level set takes it from there
+    without timing (the same shapes, the file unchanged)."""
+    Z = z4c()
+    bt = W.random_batch(12, nblocks=3, nmax=20, fd_order=6)
+    path = tmp_path / "tune.txt"
+    Z.set_tune_cache(path)
+    try:
+        note("autotune cache")
+        u0, out, u1 = dev(bt.u), dev(bt.u), dev(bt.u)
+        p1 = Z.plan_for(bt)
+        p1.autotune(u0, out, u1, dev(bt.matter), reps=1)
+        text = path.read_text()
+        assert len(text.strip().splitlines()) == len({(b.nx, b.ny, b.nz) for b in bt.blocks})
+        assert "gfx950" in text and ":p6:" in text
+        p2 = Z.plan_for(bt)
+        p2.autotune(u0, out, u1, dev(bt.matter), reps=1)
+        for b in bt.blocks:
+            assert p1.get_launch(b.nx, b.ny, b.nz) == p2.get_launch(b.nx, b.ny, b.nz)
+        assert path.read_text() == text
+        # the tuned plan still matches the oracle
+        g = gpu_rhs(bt, plan=p2)
+        rows = compare(bt, g, O.rhs(bt), O.rhs(bt, ext=True))
+        assert_parity(rows, "autotuned rhs\n" + report(rows))
+    finally:
+        Z.set_tune_cache(None)
