@@ -260,6 +260,12 @@ z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *f
                                       the constraints of y_n (regs[0] on entry) into
                                       cons (may be NULL) and norms, as
                                       z4c_rk_stage_monitor; no extra pass */
+#define Z4C_STEP_LEVEL_EXCHANGE 8  /* multi-level set: after every stage the stored
+                                      ghosts of its output are refreshed by the
+                                      same-level policy, then exchanged across the
+                                      level jumps set with
+                                      z4c_plan_set_level_exchange (implies stored
+                                      ghosts) */
 typedef struct {
     double *regs[4];
     const double *matter;
@@ -374,6 +380,20 @@ z4c_status z4c_level_transfers(const z4c_plan *plan, const z4c_loc *locs, int co
  * array `u` (device, the plan's layout), asynchronously on the stream. */
 z4c_status z4c_prolongate(const z4c_xplan *xplan, double *u, void *hip_stream);
 z4c_status z4c_restrict(const z4c_xplan *xplan, double *u, void *hip_stream);
+
+/* Transfer plans of the level jumps of a multi-level set (Sec. 3.1: all
+ * levels advance with one global time step, no subcycling; Sec. 3.2:
+ * vertex-centred restriction and prolongation), one per pair of adjacent
+ * levels (from z4c_level_transfers), coarsest pair first; n = 0 removes
+ * them.  Each must have been created on this plan and outlive its use.
+ * With Z4C_STEP_LEVEL_EXCHANGE a step refreshes, after every stage, the
+ * stored ghosts of the stage output: the step's ghost policy (same-level
+ * copies, frozen outer faces), then every restriction (coarse ghosts inside
+ * finer blocks, injected from their vertices) finest pair first, then every
+ * prolongation (fine ghosts inside coarser blocks, interpolated from coarse
+ * points whose ghosts are then current) coarsest pair first. */
+z4c_status z4c_plan_set_level_exchange(z4c_plan *plan, const z4c_xplan *const *xplans, int n);
+
 
 const char *z4c_strerror(z4c_status status);
 const char *z4c_last_error(void);

@@ -671,6 +671,12 @@ z4c_status z4c_level_transfers(const z4c_plan *plan, const z4c_loc *locs, int co
     return Z4C_OK;
 }
 
+}  // extern "C"
+
+const z4c_plan *z4c::xplan_plan(const z4c_xplan *X) { return X ? X->plan : nullptr; }
+
+extern "C" {
+
 z4c_status z4c_prolongate(const z4c_xplan *X, double *u, void *stream)
 {
     return xcall(X, u, true, (hipStream_t)stream);

@@ -112,6 +112,8 @@ hipError_t launch_zero_queue(int *q, hipStream_t s);
 // its device copy (nullptr without a device).
 const std::vector<z4c_block> &plan_blocks(const z4c_plan *P);
 const z4c_block *plan_blocks_device(const z4c_plan *P);
+// The plan a transfer plan was created on.
+const z4c_plan *xplan_plan(const z4c_xplan *X);
 
 // Last-error message of the calling thread (z4c_last_error), for the host
 // code of every translation unit; both return their status argument.

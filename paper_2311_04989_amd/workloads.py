@@ -470,6 +470,24 @@ def random_batch(seed: int, nblocks: int = 3, nmax: int = 40, ng=None, fd_order=
     return bt
 
 
+def level_neighbours(bt: Batch, locs) -> np.ndarray:
+    """Same-level neighbour table of a level set (nblocks x 27, -1 where the
+    adjacent position holds no block of the same level): the block of level
+    L whose vertex 0 sits n steps further in that direction."""
+    lmax = max(L for L, _ in locs)
+    where = {(L, tuple(o)): b for b, (L, o) in enumerate(locs)}
+    nbr = np.full((len(bt.blocks), 27), -1, dtype=np.int32)
+    for b, (blk, (L, o)) in enumerate(zip(bt.blocks, locs)):
+        s = 1 << (lmax - L)
+        for oz in (-1, 0, 1):
+            for oy in (-1, 0, 1):
+                for ox in (-1, 0, 1):
+                    key = (L, (o[0] + ox * blk.nx * s, o[1] + oy * blk.ny * s,
+                               o[2] + oz * blk.nz * s))
+                    nbr[b, dir_index(ox, oy, oz)] = where.get(key, -1)
+    return nbr
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 

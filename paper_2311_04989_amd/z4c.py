@@ -22,7 +22,7 @@ ARITH_FP64, ARITH_FP32, ARITH_FP32_NAIVE = 0, 1, 2
 ADVECT_CENTRED, ADVECT_LOPSIDED = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
-STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL, STEP_MONITOR = 1, 2, 4
+STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL, STEP_MONITOR, STEP_LEVEL_EXCHANGE = 1, 2, 4, 8
 
 
 class Params(ctypes.Structure):
@@ -170,6 +170,8 @@ def lib():
                                           ctypes.POINTER(Transfer), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]
         L.z4c_restrict.argtypes = [vp, vp, vp]
+        L.z4c_plan_set_level_exchange.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int]
+        L.z4c_plan_set_level_exchange.restype = st
         for name in ("z4c_xplan_create", "z4c_xplan_destroy", "z4c_prolongate", "z4c_restrict",
                      "z4c_level_transfers"):
             getattr(L, name).restype = st
@@ -273,6 +275,12 @@ class Plan:
 
     def set_halo(self, policy, frozen=None):
         _check(lib().z4c_plan_set_halo(self._h, int(policy), _ptr(frozen)))
+
+    def set_level_exchange(self, xplans):
+        """Transfer plans (XPlan) of the level jumps, coarsest pair first."""
+        arr = (ctypes.c_void_p * max(1, len(xplans)))(*[x._h.value for x in xplans])
+        self._levels = list(xplans)   # keep them alive while the plan uses them
+        _check(lib().z4c_plan_set_level_exchange(self._h, arr, len(xplans)))
 
     def set_launch(self, nx, ny, nz, tile=(8, 8, 8), persistent=0, waves=2):
         L = Launch(tile[0], tile[1], tile[2], persistent, waves)
