@@ -154,7 +154,15 @@ z4c_status z4c_plan_set_params(z4c_plan *plan, const z4c_params *params);
 
 /* Same-level neighbour table (HOST, nblocks*27 ints, -1 = outer boundary),
  * entry [b*27 + (oz+1)*9 + (oy+1)*3 + (ox+1)] = block adjacent to b in
- * direction (ox, oy, oz).  Neighbours must have equal nx, ny, nz, ng. */
+ * direction (ox, oy, oz).  Neighbours must have equal nx, ny, nz, ng and
+ * field_stride.  Halo reads through the neighbour rule address a point of
+ * another block by its 32-bit element offset from the state array base, so
+ * they need offset + (nx+2ng)(ny+2ng)(nz+2ng) <= 2^32 for every block named
+ * as another block's neighbour (34 GB of FP64 before its end); a table that
+ * breaks this is accepted (ghost refreshes address in 64 bits) unless the
+ * plan reads halos through the neighbour rule (Z4C_ENOTSUP, plan unchanged).
+ * A block's own points, its periodic images and `frozen` have no such
+ * limit. */
 z4c_status z4c_plan_set_neighbours(z4c_plan *plan, const int *neighbours);
 
 /* Launch shape for the blocks of one size class (nx, ny, nz) (0 = all).
@@ -179,7 +187,7 @@ z4c_status z4c_plan_get_launch(const z4c_plan *plan, int nx, int ny, int nz, z4c
  * `frozen`) and FROZEN read, for every ghost point, the value a
  * z4c_ghost_fill with that policy would store there — straight from the
  * source, so no refresh pass is needed and the stored ghosts are ignored.
- * Rule-based reads need offset + 22*field_stride < 2^32 for every block
+ * NEIGHBOUR needs the offset limit stated at z4c_plan_set_neighbours
  * (Z4C_ENOTSUP otherwise).  `frozen` (device, state layout) must stay valid
  * while calls that use it are pending. */
 z4c_status z4c_plan_set_halo(z4c_plan *plan, int policy, const double *frozen);
@@ -202,9 +210,7 @@ z4c_status z4c_rk_stage(z4c_plan *plan, const double *u0_in, double *u0_out, dou
  * `cons` (constraint layout, may be NULL) and per-block norms into `norms`
  * (device, nblocks*16 doubles: for field q, [b*16+2q] = sum |c| dV and
  * [b*16+2q+1] = sum c^2 dV, dV = dx dy dz), summed in a fixed order.
- * Needs offset + 22*field_stride < 2^32 for every block (Z4C_ENOTSUP
- * otherwise: the constraint kernel addresses its halo from the array base
- * with 32-bit element offsets). */
+ * Halo reads follow z4c_plan_set_halo. */
 z4c_status z4c_constraints(z4c_plan *plan, const double *u, const double *matter,
                            double *cons, double *norms, void *stream);
 
@@ -247,7 +253,11 @@ z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *f
  * between stages; the ghosts of the final state are then refreshed once
  * (unless Z4C_STEP_NO_FINAL_FILL).  Z4C_STEP_STORED_GHOSTS instead refreshes
  * the stored ghosts of every stage output with z4c_ghost_fill and lets the
- * stages read them; both give bitwise the same interior.  Buffers regs[0..3]:
+ * stages read them; both give bitwise the same interior.  The step takes
+ * that form by itself under the neighbour policy when the neighbour table
+ * breaks the offset limit of z4c_plan_set_neighbours, and then first
+ * refreshes the ghosts of regs[0] (which halo reads would not read), so
+ * that the result is the same.  Buffers regs[0..3]:
  * regs[0] holds y_n on entry; regs[1], regs[2] are stage ping-pong buffers;
  * regs[3] is the accumulator.  Stage s reads regs[in_s] (in_0 = 0) and
  * writes regs[out_s]: the one of {1, 2} it does not read, except that the

@@ -181,7 +181,10 @@ struct z4c_plan {
     int *nbr_d = nullptr;
     bool has_nbr = false;
     bool periodic_ok = true;   // every block has nx, ny, nz >= ng
-    bool offsets32 = true;     // offset + 22 field_stride < 2^32 for every block
+    // every block the neighbour table names for another block ends within
+    // 2^32 elements of the array base (halo reads address such points with
+    // 32-bit element offsets from the base)
+    bool nbr32 = true;
     int halo = Z4C_GHOST_NONE; // halo reads of z4c_rhs / z4c_rk_stage / z4c_constraints
     // level-jump exchange of Z4C_STEP_LEVEL_EXCHANGE: one transfer plan per
     // pair of adjacent levels, coarsest pair first
@@ -488,11 +491,11 @@ z4c_status validate_halo(const z4c_plan *P, int policy, const double *frozen)
         return fail(Z4C_EINVAL, "unknown ghost policy");
     if (policy == Z4C_GHOST_NONE)
         return Z4C_OK;
-    if (!P->offsets32)
-        return fail(Z4C_ENOTSUP, "halo reads through a ghost rule need offset + 22*field_stride "
-                                 "< 2^32 for every block");
     if (policy == Z4C_GHOST_NEIGHBOUR && !P->has_nbr)
         return fail(Z4C_EINVAL, "neighbour policy needs z4c_plan_set_neighbours first");
+    if (policy == Z4C_GHOST_NEIGHBOUR && !P->nbr32)
+        return fail(Z4C_ENOTSUP, "neighbour-rule halo reads need offset + stored points <= 2^32 "
+                                 "for every block that is another block's neighbour");
     if (policy == Z4C_GHOST_PERIODIC && !P->periodic_ok)
         return fail(Z4C_EINVAL, "periodic refresh needs nx, ny, nz >= ng for every block");
     if ((policy == Z4C_GHOST_FROZEN || policy == Z4C_GHOST_NEIGHBOUR) && !frozen) {
@@ -600,8 +603,18 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
     // (no refresh pass) unless stored ghosts are asked for or unavailable;
     // a level-jump exchange works on stored ghosts.
     const bool levels = (d->flags & Z4C_STEP_LEVEL_EXCHANGE) != 0;
+    // Neighbour-rule halo reads beyond their offset limit: stored ghosts
+    // instead, those of y_n refreshed first (halo reads would ignore them),
+    // so that both forms read the same values.
+    const bool fallback = !(d->flags & Z4C_STEP_STORED_GHOSTS) && !levels
+                          && d->ghost_policy == Z4C_GHOST_NEIGHBOUR && !P->nbr32;
     const bool stored = (d->flags & Z4C_STEP_STORED_GHOSTS) || d->ghost_policy == Z4C_GHOST_NONE
-                        || !P->offsets32 || levels;
+                        || fallback || levels;
+    if (fallback) {
+        st = enqueue_ghost(P, d->ghost_policy, d->regs[0], d->frozen, s);
+        if (st != Z4C_OK)
+            return st;
+    }
     for (int k = 0; k < d->nstages; ++k) {
         const double *y = d->regs[0];
         const bool mon = k == 0 && (d->flags & Z4C_STEP_MONITOR);
@@ -647,9 +660,6 @@ z4c_status validate_constraints(const z4c_plan *P, const double *u, const double
         return fail(Z4C_EINVAL, "outputs must not alias u or each other");
     if (!aligned8(u) || !aligned8(cons) || !aligned8(norms) || !aligned8(matter))
         return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
-    if (!P->offsets32)
-        return fail(Z4C_ENOTSUP, "constraints need offset + 22*field_stride < 2^32 for every "
-                                 "block (32-bit element offsets from the state array base)");
     return need_device(P);
 }
 
@@ -856,8 +866,6 @@ z4c_status z4c_plan_create(const z4c_params *params, const z4c_block *blocks, in
         gs[b + 1] = gs[b] + ex * ey * ez - interior;
         if (B.nx < B.ng || B.ny < B.ng || B.nz < B.ng)
             P->periodic_ok = false;
-        if (B.offset + 22LL * B.field_stride > 0xFFFFFFFFLL)
-            P->offsets32 = false;
         ps[b + 1] = ps[b] + interior;
     }
     P->total_ghost = gs[nblocks];
@@ -973,11 +981,18 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
 {
     if (!P || !nbr)
         return fail(Z4C_EINVAL, "plan and neighbour table must not be NULL");
+    bool far32 = true;
     for (int b = 0; b < P->nblocks; ++b)
         for (int d = 0; d < 27; ++d) {
             const int n = nbr[b * 27 + d];
             if (n < -1 || n >= P->nblocks)
                 return fail(Z4C_EINVAL, "neighbour index out of range");
+            if (n >= 0 && n != b) {
+                const z4c_block &N = P->blocks[n];
+                const long long npts = (N.nx + 2LL * N.ng) * (N.ny + 2LL * N.ng) * (N.nz + 2LL * N.ng);
+                if (N.offset + npts > (1LL << 32))
+                    far32 = false;
+            }
             if (n >= 0) {
                 const z4c_block &A = P->blocks[b], &B = P->blocks[n];
                 if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.ng != B.ng
@@ -989,6 +1004,10 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
                     return fail(Z4C_EINVAL, "a neighbour copy needs n >= ng along its direction");
             }
         }
+    if (!far32 && P->halo == Z4C_GHOST_NEIGHBOUR)
+        return fail(Z4C_ENOTSUP, "the plan reads halos through the neighbour rule, which needs "
+                                 "offset + stored points <= 2^32 for every block that is another "
+                                 "block's neighbour");
     if (P->device) {
         if (!P->nbr_d)
             HIP_TRY(hipMalloc(&P->nbr_d, sizeof(int) * 27 * P->nblocks), "hipMalloc(neighbours)");
@@ -997,6 +1016,7 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
         P->clear_graphs();
     }
     P->has_nbr = true;
+    P->nbr32 = far32;
     ++P->version;
     return Z4C_OK;
 }

@@ -556,25 +556,29 @@ __device__ __forceinline__ Fac<R> load_fac(const StageArgs &a, int block)
 
 // Halo-tile staging of one field at a time: registers <- HBM (prefetch of
 // the next field), LDS <- registers (between two barriers).  Each halo
-// element has a 32-bit element offset from the state (or frozen) array base
-// of field 0, found once per tile: the point itself, or, for ghost points
-// under a refresh rule, the point a refresh would copy.
+// element has a 32-bit element offset found once per tile: from the block's
+// own base of field 0 for its own points and stored ghosts, the periodic
+// image and the same point of `frozen`; from the state array base for
+// another block's point under the neighbour rule (the plan refuses that rule
+// unless such offsets stay below 2^32).  Blocks of the first kind may lie
+// anywhere in the state array.
 template <int NLD>
 struct Stager {
     int ldo[NLD];
     unsigned src[NLD];
-    unsigned valid, frz;    // bit q: element q is loaded / comes from `frozen`
+    unsigned valid, frz, far;   // bit q: element q is loaded / from `frozen` / from another block
     double pf[NLD];
-    const double *u, *frozen;
+    const double *own, *own_frozen, *all;   // u + offset, frozen + offset, u
     long long fs;
 
     __device__ __forceinline__ void prefetch(int f)
     {
-        const double *bu = u + (long long)f * fs;   // uniform
-        const double *bf = frozen + (long long)f * fs;
+        const long long e = (long long)f * fs;   // uniform
 #pragma unroll
         for (int q = 0; q < NLD; ++q)
-            pf[q] = (valid >> q) & 1u ? ((frz >> q) & 1u ? bf : bu)[src[q]] : 0.0;
+            pf[q] = (valid >> q) & 1u
+                        ? ((far >> q) & 1u ? all + e : (frz >> q) & 1u ? own_frozen + e : own + e)[src[q]]
+                        : 0.0;
     }
     __device__ __forceinline__ void store(double *lds)
     {
@@ -593,12 +597,13 @@ __device__ __forceinline__ void setup_stager(Stager<NLD> &st, const StageArgs &a
     const int ng = B.ng;
     const int sy = B.nx + 2 * ng;
     const int sz = sy * (B.ny + 2 * ng);
-    st.u = a.u;
-    st.frozen = a.frozen;
+    st.own = a.u + B.offset;
+    st.own_frozen = a.frozen ? a.frozen + B.offset : nullptr;
+    st.all = a.u;
     st.fs = B.field_stride;
     st.valid = 0u;
     st.frz = 0u;
-    const unsigned own = (unsigned)B.offset;
+    st.far = 0u;
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
         const int e = t + q * NT;
@@ -613,7 +618,7 @@ __device__ __forceinline__ void setup_stager(Stager<NLD> &st, const StageArgs &a
                 const int ox = gi < 0 ? -1 : (gi >= B.nx ? 1 : 0);
                 const int oy = gj < 0 ? -1 : (gj >= B.ny ? 1 : 0);
                 const int oz = gk < 0 ? -1 : (gk >= B.nz ? 1 : 0);
-                unsigned idx = own + (unsigned)((gk + ng) * sz + (gj + ng) * sy + (gi + ng));
+                unsigned idx = (unsigned)((gk + ng) * sz + (gj + ng) * sy + (gi + ng));
                 if ((ox | oy | oz) != 0 && a.halo != Z4C_GHOST_NONE) {
                     int sb = -1;
                     if (a.halo == Z4C_GHOST_PERIODIC)
@@ -623,8 +628,11 @@ __device__ __forceinline__ void setup_stager(Stager<NLD> &st, const StageArgs &a
                     if (sb >= 0) {
                         // same nx, ny, nz, ng and field stride as this block
                         const int si = gi - ox * B.nx, sj = gj - oy * B.ny, sk = gk - oz * B.nz;
-                        idx = (unsigned)a.blocks[sb].offset
-                            + (unsigned)((sk + ng) * sz + (sj + ng) * sy + (si + ng));
+                        idx = (unsigned)((sk + ng) * sz + (sj + ng) * sy + (si + ng));
+                        if (sb != T.block) {
+                            idx += (unsigned)a.blocks[sb].offset;
+                            st.far |= 1u << q;
+                        }
                     } else if (a.frozen) {
                         st.frz |= 1u << q;
                     }   // else: the stored ghost, which a refresh leaves as it is

@@ -257,8 +257,11 @@ def test_strerror_names_every_status():
 
 
 def test_size_limits_of_32_bit_addressing():
-    """Blocks of 2^29 or more stored points, and constraints over arrays whose
-    element offsets exceed 32 bits, are refused before anything runs."""
+    """Blocks of 2^29 or more stored points are refused; a block far into the
+    state array (element offset 2^32) is fine for periodic halo reads and
+    constraints (block-relative offsets), and refused only as another
+    block's neighbour under the neighbour rule, whichever of the table and
+    the rule comes first, leaving the plan as it was."""
     p = Z.make_params(W.Params(fd_order=6))
     big = np.zeros(1, dtype=W.BLOCK_DTYPE)
     n = 812                                   # (812 + 8)^3 = 551,368,000 >= 2^29
@@ -274,11 +277,43 @@ def test_size_limits_of_32_bit_addressing():
     far[0] = (0, 0, 0, 24 ** 3, 16, 16, 16, 4, 1.0, 1.0, 1.0)
     far[1] = (1 << 32, 0, 0, 24 ** 3, 16, 16, 16, 4, 1.0, 1.0, 1.0)
     plan = Z.Plan(p, Z.make_blocks(far), Z.PLAN_NO_DEVICE)
-    with pytest.raises(Z.Z4cError) as e:
+    with pytest.raises(Z.Z4cError) as e:       # validation passes; no device to run on
         plan.constraints(8, None, 16, 24)
+    assert e.value.status == Z.ENODEV
+    plan.set_halo(Z.GHOST_PERIODIC)
+    plan.set_halo(Z.GHOST_FROZEN, 64)
+    # block 1 neighbours block 0 (and itself): its points are near the base
+    own = np.full((2, 27), -1, dtype=np.int32)
+    own[0, 13] = 0
+    own[1, 13] = 1
+    own[1, 12] = 0                             # block 1's -x neighbour is block 0
+    plan.set_neighbours(own)
+    plan.set_halo(Z.GHOST_NEIGHBOUR, 64)
+    # block 0's +x neighbour is block 1, which ends beyond 2^32 elements
+    bad = own.copy()
+    bad[0, 14] = 1
+    with pytest.raises(Z.Z4cError) as e:       # refused while the rule is in use
+        plan.set_neighbours(bad)
     assert e.value.status == Z.ENOTSUP
+    plan.set_halo(Z.GHOST_NEIGHBOUR, 64)      # the earlier table is still in place
+    plan.set_halo(Z.GHOST_PERIODIC)
+    plan.set_neighbours(bad)                   # accepted for ghost refreshes
     with pytest.raises(Z.Z4cError) as e:
-        plan.set_halo(Z.GHOST_PERIODIC)
+        plan.set_halo(Z.GHOST_NEIGHBOUR, 64)
+    assert e.value.status == Z.ENOTSUP
+    plan.close()
+    # the limit is on the neighbour's end: offset + stored points <= 2^32
+    edge = far.copy()
+    edge[1]["offset"] = (1 << 32) - 24 ** 3
+    plan = Z.Plan(p, Z.make_blocks(edge), Z.PLAN_NO_DEVICE)
+    plan.set_neighbours(bad)
+    plan.set_halo(Z.GHOST_NEIGHBOUR, 64)
+    edge[1]["offset"] += 1
+    plan.close()
+    plan = Z.Plan(p, Z.make_blocks(edge), Z.PLAN_NO_DEVICE)
+    plan.set_neighbours(bad)
+    with pytest.raises(Z.Z4cError) as e:
+        plan.set_halo(Z.GHOST_NEIGHBOUR, 64)
     assert e.value.status == Z.ENOTSUP
     plan.close()
 
