@@ -10,15 +10,20 @@ e_oracle is the same error of the FP64 oracle against o.  On fields whose
 value is a near-cancellation of much larger terms (Theta on constraint-
 satisfying data, At on the star metric) the FP64 oracle itself is only
 good to a few 1e-12; there the GPU must be within 8x of the oracle's own
-rounding error, elsewhere within 1e-12.  Fields that are exactly zero in
-the oracle must be exactly zero on the GPU.
+rounding error, elsewhere within 1e-12.  Why 8: the two evaluation orders
+put each term of the longest sums (32 terms) through between 5 and 31
+roundings, so their random-like rounding errors have spreads within a
+factor (31/5)^(1/2) = 2.5 of each other, and the maximum over many points
+moves that ratio by some 20 %; 8 is the power of two above twice 2.5 x 1.2.
+Fields that are exactly zero in the oracle must be exactly zero on the GPU.
 
 State outputs (a stage or a step) are compared through their increments
 (state minus a base state), since states near 1 would make the comparison
-vacuous.  Every implementation rounds the stored state to double, and a
-different but correctly rounded sequence (a fused multiply-add) can land
-one or two units in the last place (ulp) away; so for increments the
-error first has 4 ulp of the stored state value subtracted:
+vacuous.  The stage combination rounds up to six times at the magnitude of
+the state on the GPU (two fused steps for u1, four for u0'), half an ulp
+each, and the extended oracle once when it stores double: 3.5 units in the
+last place (ulp), so for increments the error first has 4 ulp of the
+stored state value subtracted:
     e(p) = max(|g - o| - 4 ulp(|x(p)|), 0) / max(|o|, tau_f).
 """
 import numpy as np
