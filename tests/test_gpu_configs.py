@@ -2,7 +2,8 @@
 the chi/alpha floors (enforcement after a stage and max(chi, chi_floor) in
 every 1/chi), the harmonic and frozen lapse, the frozen shift and no gauge
 advection; the right-hand side of every stage inside full Runge-Kutta
-steps (held to the right-hand-side gate, not only to the step increments);
+steps (held to the right-hand-side gate, not only to the step increments),
+on the gauge wave, the uneven level set and the full-size star level set;
 and launch-to-launch reproducibility of the stage kernel at full size.
 """
 import sys
@@ -222,6 +223,20 @@ def test_config4_every_stage_rhs_at_the_rhs_gate_sampled():
                           for s in (8, 16, 24, 32)])
     _, worst = _stagewise(bt, plan, idx)
     note(f"config4 stagewise worst e/tol {worst:.3f}")
+    plan.close()
+
+
+def test_config5_full_size_every_stage_rhs_at_the_rhs_gate_sampled():
+    """The full star level set (8 blocks of 128^3 with matter, neighbour
+    ghosts between the blocks, frozen outer ghosts): one RK4 step stage by
+    stage, each stage's right-hand side of block 6 (three neighbour faces,
+    three frozen faces) against the oracle at the right-hand-side gate."""
+    Z = Zm()
+    bt = W.config5()
+    note("config5 full size stagewise (block 6)")
+    plan = Z.plan_for(bt)
+    _, worst = _stagewise(bt, plan, [6])
+    note(f"config5 stagewise worst e/tol {worst:.3f}")
     plan.close()
 
 
