@@ -5,7 +5,8 @@ ghosts and frozen outer ghosts.
 
 The same RK4 evolution (global dt = dx/4) runs once with FP64 arithmetic and
 once with FP32 arithmetic (FP64 storage, stencil differences and Runge-Kutta
-combination).  Reported: time per step of each; at every checkpoint the L2
+combination), each in its own autotuned launch shapes.  Reported: time per
+step of each; at every checkpoint the L2
 norms of the Hamiltonian and momentum constraints of each run and the L2 norm
 of the difference of the two Hamiltonian-constraint fields; at the end, per
 state field, the largest relative difference of the FP32 state from the FP64
@@ -42,6 +43,9 @@ def evolve(bt, arith, steps, every, stream, h_ref=None):
     norms = torch.zeros(len(bt.blocks) * 16, dtype=torch.float64, device=dev)
     plan.set_halo(Z.GHOST_NEIGHBOUR, frozen)
     plan.ghost_fill(Z.GHOST_NEIGHBOUR, regs[0], frozen, stream=stream)
+    # launch shapes tuned for each arithmetic, so that the two runs compare
+    # at their best (regs[1] and regs[3] are scratch until the first step)
+    plan.autotune(regs[0], regs[1], regs[3], matter, reps=3, stream=stream)
     dv = bt.blocks[0].dx * bt.blocks[0].dy * bt.blocks[0].dz
     hslices = [slice(int(bt.coffsets[b]), int(bt.coffsets[b] + bt.field_stride[b]))
                for b in range(len(bt.blocks))]
