@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration), then "
                          "--steps launches of RK4 stage 2 in the autotuned configuration")
+    ap.add_argument("--profile-arith", choices=("fp64", "fp32"), default="fp64",
+                    help="arithmetic of the --profile launches")
     ap.add_argument("--cpu-sample-blocks", type=int, default=0,
                     help="oracle sample size (0: the whole level set)")
     ap.add_argument("--matter-only", action="store_true",
@@ -121,7 +123,7 @@ def main():
     stream = torch.cuda.current_stream()
     Z.set_tune_cache(args.tune_cache or None)
     if args.profile:
-        profile_run(args.steps, stream)
+        profile_run(args.steps, stream, args.profile_arith)
         return
     if args.matter_only:
         print(json.dumps(matter_coupling(stream, args.steps)), flush=True)
@@ -443,11 +445,12 @@ def monitor_timing(plan, regs, bt, stream, reps):
     return out
 
 
-def profile_run(launches, stream):
+def profile_run(launches, stream, arith="fp64"):
     """What the committed counter profiles ran: a device copy of 2^27 doubles
     (1 GiB read, 1 GiB written) to calibrate FETCH_SIZE / WRITE_SIZE, then RK4
     stage 2 (reads u0, u1, u2; writes u1, u0') of the uneven level set with
-    ghosts read through the periodic rule, in the autotuned launch shapes."""
+    ghosts read through the periodic rule, in the autotuned launch shapes, with
+    FP64 or FP32 arithmetic."""
     import torch
 
     from paper_2311_04989_amd import workloads as W
@@ -459,7 +462,7 @@ def profile_run(launches, stream):
     torch.cuda.synchronize()
     del a, b
     bt = W.config4()
-    plan = Z.plan_for(bt, Z.ARITH_FP64)
+    plan = Z.plan_for(bt, Z.ARITH_FP32 if arith == "fp32" else Z.ARITH_FP64)
     u = torch.from_numpy(bt.u).to("cuda:0")
     regs = [u.clone(), u.clone(), u.clone(), u.clone()]
     plan.ghost_fill(Z.GHOST_PERIODIC, regs[0], stream=stream)
@@ -467,7 +470,7 @@ def profile_run(launches, stream):
     plan.autotune(regs[0], regs[1], regs[3], None, reps=3, stream=stream)
     torch.cuda.synchronize()
     shapes = {s: plan.get_launch(s, s, s) for s in (8, 16, 24, 32)}
-    log(f"[profile] launch shapes {shapes}; {launches} launches of RK4 stage 2")
+    log(f"[profile] {arith}: launch shapes {shapes}; {launches} launches of RK4 stage 2")
     for _ in range(launches):
         plan.rk_stage(regs[0], regs[1], regs[3], regs[2], None, Z.RK4[1], bt.dt, stream=stream)
     torch.cuda.synchronize()
