@@ -422,7 +422,9 @@ __device__ __forceinline__ int first_tile(const StageArgs &a, int t, int *slot)
     return *slot;
 }
 
-// Called by every thread after the tile's closing barrier.
+// Called by every thread at the end of a tile.  Every thread read the slot
+// right after the barrier that published it, before the tile's staging
+// barriers, so thread 0 cannot overwrite it early.
 __device__ __forceinline__ int next_tile(const StageArgs &a, int t, int *slot)
 {
     if (!a.persistent)
