@@ -300,10 +300,14 @@ z4c_status z4c_step_graph(z4c_plan *plan, const z4c_step_desc *desc, int *result
  * (u0 read, u0_out/u1 overwritten at interior points, one RK4-like stage)
  * and keep the fastest; `reps` timed launches per candidate.  Candidates:
  * every supported tile shape and occupancy, each as a grid launch and as
- * persistent launches of one and two workgroups per CU.  With a tuning
- * cache set (z4c_set_tune_cache), size classes found there under the same
- * key (device architecture, order, arithmetic, advection, halo rule, block
- * interior size, ghosts) take the stored shape without timing, and newly
+ * persistent launches of one and two workgroups per CU.  Then classes that
+ * chose the same tile shape and occupancy are timed together, as they
+ * launch (one dispatch when their launch forms agree), under their own
+ * choices and under each common launch form, and the fastest is kept.
+ * With a tuning cache set (z4c_set_tune_cache), size classes found there
+ * under the same key (device architecture, order, arithmetic, advection,
+ * halo rule, block interior size, ghosts) take the stored launch without
+ * timing (and without the joint pass when every class is found), and newly
  * timed ones are added to it.  Results are readable with
  * z4c_plan_get_launch.  Synchronises the stream. */
 z4c_status z4c_plan_autotune(z4c_plan *plan, const double *u0, double *u0_out, double *u1,

@@ -686,7 +686,8 @@ z4c_status enqueue_constraints(z4c_plan *P, const double *u, const double *matte
 // Autotuning cache: one line per size class and scheme,
 //   <key> <tile_x> <tile_y> <tile_z> <persistent> <waves> <ms per launch>
 // keyed by the device architecture, order, arithmetic, advection, halo rule
-// and the block's interior and ghost sizes.  The path is set with
+// and the block's interior and ghost sizes; the time is that of the launch
+// that made the choice (the class alone, or the merged set it joined).  The path is set with
 // z4c_set_tune_cache (empty: no cache).
 struct TuneEntry {
     z4c_launch launch;
@@ -1375,6 +1376,75 @@ z4c_status z4c_plan_autotune(z4c_plan *P, const double *u0, double *u0_out, doub
         }
         if (st != Z4C_OK)
             break;
+    }
+    // Merge pass.  Classes that share a tile shape and occupancy run as one
+    // dispatch when they also share the launch form, which a class timed
+    // alone cannot see (one tail instead of several, one work queue for
+    // all).  For each such set of two or more classes, time the set with
+    // the per-class choices and with each uniform launch form, and keep the
+    // fastest (a change must be 1.5 % faster).  Runs only when some class was
+    // timed now, so that a plan whose classes all come from the cache keeps
+    // exactly the cached launches.
+    bool fresh_any = false;
+    for (size_t ci = 0; ci < saved.size(); ++ci)
+        fresh_any = fresh_any || best_time[ci] >= 0.f;
+    if (st == Z4C_OK && fresh_any) {
+        std::map<std::vector<int>, std::vector<size_t>> sets;
+        for (size_t ci = 0; ci < saved.size(); ++ci)
+            sets[{best[ci].tile_x, best[ci].tile_y, best[ci].tile_z, best[ci].waves}].push_back(ci);
+        auto time_set = [&](const std::vector<size_t> &members,
+                            const std::vector<z4c_launch> &launch, float *ms) -> z4c_status {
+            P->classes.clear();
+            for (size_t m = 0; m < members.size(); ++m) {
+                P->classes.push_back(saved[members[m]]);
+                P->classes.back().launch = launch[m];
+            }
+            z4c_status r = build_groups(P);
+            if (r == Z4C_OK)
+                r = enqueue_stage(P, u0, u0_out, u1, u0, matter, &c, 1e-3, s);   // warm-up
+            if (r != Z4C_OK)
+                return r;
+            (void)hipEventRecord(e0, s);
+            for (int k = 0; k < reps && r == Z4C_OK; ++k)
+                r = enqueue_stage(P, u0, u0_out, u1, u0, matter, &c, 1e-3, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            *ms = 0.f;
+            (void)hipEventElapsedTime(ms, e0, e1);
+            return r;
+        };
+        for (const auto &kv : sets) {
+            const std::vector<size_t> &members = kv.second;
+            if (members.size() < 2)
+                continue;
+            std::vector<z4c_launch> cur(members.size());
+            for (size_t m = 0; m < members.size(); ++m)
+                cur[m] = best[members[m]];
+            float best_ms = 0.f;
+            st = time_set(members, cur, &best_ms);
+            std::vector<z4c_launch> pick = cur;
+            for (int pers : {0, 1, 2}) {
+                if (st != Z4C_OK)
+                    break;
+                std::vector<z4c_launch> uni(members.size(), cur[0]);
+                for (auto &L : uni)
+                    L.persistent = pers * P->num_cus;
+                float ms = 0.f;
+                st = time_set(members, uni, &ms);
+                if (st == Z4C_OK && ms < 0.985f * best_ms) {
+                    best_ms = ms;
+                    pick = uni;
+                }
+            }
+            if (st != Z4C_OK)
+                break;
+            for (size_t m = 0; m < members.size(); ++m) {
+                const size_t ci = members[m];
+                if (pick[m].persistent != best[ci].persistent)
+                    best_time[ci] = best_ms / reps;   // now a member of a merged dispatch
+                best[ci] = pick[m];
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
