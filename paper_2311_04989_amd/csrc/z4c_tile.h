@@ -364,6 +364,23 @@ __device__ __forceinline__ void second(const double *c, const Fac<R> &F, R dd[6]
     dd[4] = dmixraw<P, R, PX, PXY>(c) * F.mix[2];
 }
 
+// As second, with the mixed derivatives from the two-pass sums of mix_prep
+// (dxb, dyb) instead of the tensor-product stencil.
+template <int P, typename R, int PX, int PXY, int TX, int TY, int TZ>
+__device__ __forceinline__ void second_sums(const double *c, const Fac<R> &F, R dd[6],
+                                            const R *dxb, const R *dyb, int tx, int ty, int tz)
+{
+    using M = MixDims<P, TX, TY, TZ>;
+    dd[0] = d2raw<P, R, 1>(c) * F.d2[0];
+    dd[3] = d2raw<P, R, PX>(c) * F.d2[1];
+    dd[5] = d2raw<P, R, PXY>(c) * F.d2[2];
+    const R *px = dxb + ((tz + M::Q) * M::DY + (ty + M::Q)) * TX + tx;
+    const R *py = dyb + ((tz + M::Q) * TY + ty) * TX + tx;
+    dd[1] = d1sum<P, R, TX>(px) * F.mix[0];
+    dd[2] = d1sum<P, R, TX * M::DY>(px) * F.mix[1];
+    dd[4] = d1sum<P, R, TX * TY>(py) * F.mix[2];
+}
+
 template <int P, typename R, int PX, int PXY>
 __device__ __forceinline__ R dissipation(const double *c, const Fac<R> &F)
 {
@@ -782,6 +799,11 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
     constexpr bool CONS = MODE == MODE_CONS;
     __shared__ double lds[PXY * LZ];
     __shared__ double red[(NT / 64) * 16];
+    // mixed second derivatives of chi and gt in two passes (as the stage
+    // kernel at one wave per SIMD): x and y first-derivative sums here
+    using MD = MixDims<P, TX, TY, TZ>;
+    __shared__ R dxb[MD::NXS];
+    __shared__ R dyb[MD::NYS];
 
     const int t = threadIdx.x;
     const int tx = t % TX, ty = (t / TX) % TY, tz = t / (TX * TY);
@@ -803,12 +825,17 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
         Stager<NLD> st;
         setup_stager<NLD, NT, RAD, LX, LY, LZ, PX, PXY>(st, a, T, B, t);
         auto stage = [&](auto FC) __attribute__((always_inline)) {
-            constexpr int NX = next_field<MODE>(decltype(FC)::value);
+            constexpr int FF = decltype(FC)::value;
+            constexpr int NX = next_field<MODE>(FF);
             __syncthreads();
             st.store(lds);
             if constexpr (NX >= 0)
                 st.prefetch(NX);
             __syncthreads();
+            if constexpr (FF == CHI || (FF >= GXX && FF <= GZZ)) {
+                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds, dxb, dyb, t);
+                __syncthreads();
+            }
         };
 
         st.prefetch(GXX);
@@ -854,7 +881,7 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
             if (active) {
                 R d[3], dd[6];
                 first<P, R, PX, PXY>(lc, F, d);
-                second<P, R, PX, PXY>(lc, F, dd);
+                second_sums<P, R, PX, PXY, TX, TY, TZ>(lc, F, dd, dxb, dyb, tx, ty, tz);
                 sfor<3>([&](auto kk_c) __attribute__((always_inline)) { constexpr int kk = decltype(kk_c)::value; { dg[kk][q] = d[kk]; } });
                 Rij[q] = R(-0.5) * symtrace(gi, dd);
                 if constexpr (!CONS)
@@ -932,7 +959,7 @@ __global__ void __launch_bounds__(TX *TY *TZ) cons_kernel(const StageArgs a)
         if (active) {
             R dd[6];
             first<P, R, PX, PXY>(lc, F, dchi);
-            second<P, R, PX, PXY>(lc, F, dd);
+            second_sums<P, R, PX, PXY, TX, TY, TZ>(lc, F, dd, dxb, dyb, tx, ty, tz);
             R DD[6];
             sfor<6>([&](auto q_c) __attribute__((always_inline)) { constexpr int q = decltype(q_c)::value; { DD[q] = dd[q] - (Gu[0][q] * dchi[0] + Gu[1][q] * dchi[1] + Gu[2][q] * dchi[2]); } });
             const R trDD = symtrace(gi, DD);
