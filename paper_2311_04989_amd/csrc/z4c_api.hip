@@ -687,8 +687,8 @@ z4c_status enqueue_constraints(z4c_plan *P, const double *u, const double *matte
 //   <key> <tile_x> <tile_y> <tile_z> <persistent> <waves> <ms per launch>
 // keyed by the device architecture, order, arithmetic, advection, halo rule
 // and the block's interior and ghost sizes; the time is that of the launch
-// that made the choice (the class alone, or the merged set it joined).  The path is set with
-// z4c_set_tune_cache (empty: no cache).
+// that made the choice (the class alone, or the merged set it joined).  The
+// path is set with z4c_set_tune_cache (empty: no cache).
 struct TuneEntry {
     z4c_launch launch;
     float ms;
