@@ -121,3 +121,42 @@ def test_naive_form_is_refused_for_stages():
     with pytest.raises(Z.Z4cError) as e:
         plan.rk_stage(u, out, torch.zeros_like(u), u, None, Z.RK4[0], 0.01)
     assert e.value.status == Z.ENOTSUP
+
+
+def test_fp32_rhs_on_the_level_set_sampled():
+    """The benchmark's FP32 configuration: the uneven level set (1,024 blocks,
+    ghosts through the periodic rule) in the launch shapes of the committed
+    autotuning cache; 16 sampled blocks (4 per size) against the FP32
+    reference gate."""
+    import os
+    from paper_2311_04989_amd import z4c as Z
+    bt = W.config4()
+    O.ghost_fill(bt, bt.u)
+    note("fp32 rhs level set, 16 sampled blocks")
+    cache = os.path.join(os.path.dirname(Z.__file__), "tune_gfx950.txt")
+    Z.set_tune_cache(cache)
+    try:
+        plan = Z.plan_for(bt, Z.ARITH_FP32)
+        u = dev(bt.u)
+        scratch = [torch.empty_like(u), torch.empty_like(u)]
+        plan.set_halo(Z.GHOST_PERIODIC)
+        plan.autotune(u, scratch[0], scratch[1], None, reps=3)
+        note(f"launch shapes {dict((n, plan.get_launch(n, n, n)) for n in (8, 16, 24, 32))}")
+        out = torch.zeros_like(u)
+        plan.rhs(u, None, out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy()
+        plan.close()
+    finally:
+        Z.set_tune_cache(None)
+    sizes = np.array([b.nx for b in bt.blocks])
+    rng = np.random.default_rng(32)
+    idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0], size=4, replace=False)
+                          for s in (8, 16, 24, 32)])
+    sub = bt.subset(idx)
+    gsub = bt.subset(idx)
+    for j, i in enumerate(idx):
+        for f in range(W.NF):
+            gsub.view(gsub.u, j, f)[...] = bt.view(g, i, f)
+    rows = compare(sub, gsub.u, O.rhs(sub, ext="f32"), O.rhs(sub, ext=True), gate=FLOOR)
+    assert_parity(rows, "fp32 level set sampled rhs (gate 8x the FP32 reference)\n" + report(rows))
