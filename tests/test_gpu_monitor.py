@@ -12,7 +12,10 @@ input (Sec. 4.1 monitoring).
   the periodic rule, autotuned shapes): constraints and norms against
   z4c_constraints on the same state (same quantities, other rounding
   order), and the stage bit for bit against z4c_rk_stage's where the
-  compiler leaves the stage's arithmetic unchanged, else within 1e-13.
+  compiler leaves the stage's arithmetic unchanged, else within 1e-13;
+* the star level set reduced to 8 x 16^3 with neighbour ghosts and frozen
+  outer ghosts read through the rule: stage and constraints against the
+  oracle.
 """
 import sys
 
@@ -241,3 +244,42 @@ def test_eager_step_with_monitor_and_stored_ghosts():
             assert np.isfinite(x).all()
             assert np.abs(x - y).max() <= 1e-9 * np.abs(y).max() + 1e-300
     plan.close()
+
+
+def test_monitor_with_neighbour_and_frozen_halo_reads():
+    """The star level set reduced to 8 blocks of 16^3 (matter, neighbour
+    ghosts between the blocks, frozen outer ghosts) read through the rule by
+    the monitor kernel in the one-wave shape: the stage and the constraints
+    against the oracle on the same state with refreshed stored ghosts."""
+    Zm = Z()
+    bt = W.config5(n=16)
+    O.ghost_fill(bt, bt.u)
+    note("monitor, neighbour + frozen halo reads, 8 x 16^3")
+    rng = np.random.default_rng(8)
+    u1_init = bt.u + rng.uniform(-1e-4, 1e-4, size=bt.u.shape)
+    c = O.RK4[1]
+    o64, o64u1 = bt.u.copy(), u1_init.copy()
+    O.rk_stage(bt, bt.u, o64, o64u1, bt.u, c, bt.dt)
+    o80, o80u1 = bt.u.copy(), u1_init.copy()
+    O.rk_stage(bt, bt.u, o80, o80u1, bt.u, c, bt.dt, ext=True)
+    c64, _ = O.constraints(bt)
+    c80, n80 = O.constraints(bt, ext=True)
+    plan = Zm.plan_for(bt)
+    plan.set_launch(0, 0, 0, tile=(8, 8, 4), persistent=0, waves=1)
+    frozen = dev(bt.frozen)
+    plan.set_halo(Zm.GHOST_NEIGHBOUR, frozen)
+    u0 = dev(bt.u)
+    out, u1 = dev(bt.u), dev(u1_init)
+    cons = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+    norms = torch.zeros(16 * len(bt.blocks), dtype=torch.float64, device=DEV)
+    plan.rk_stage_monitor(u0, out, u1, u0, dev(bt.matter), Zm.RK4[1], bt.dt, cons, norms)
+    gout, gu1, gc = host(out), host(u1), host(cons)
+    gn = host(norms).reshape(-1, 8, 2)
+    plan.close()
+    rows = compare(bt, gout, o64, o80, base=bt.u)
+    assert_parity(rows, "monitor neighbour-rule stage\n" + report(rows))
+    rows = compare(bt, gu1, o64u1, o80u1, base=u1_init)
+    assert_parity(rows, "monitor neighbour-rule accumulator\n" + report(rows))
+    rows = compare(bt, gc, c64, c80, nfields=W.NC)
+    assert_parity(rows, "monitor neighbour-rule constraints\n" + report(rows))
+    np.testing.assert_allclose(gn, n80, rtol=1e-10, atol=1e-300)
