@@ -310,6 +310,42 @@ def test_config4_graph_step_sampled():
     assert_parity(rows, "config4 sampled step increments\n" + report(rows))
 
 
+
+def test_level_set_ssprk3_graph_step_sampled():
+    """The paper's third-order Runge-Kutta (SSPRK(3,3)) on the benchmark's
+    level set, ghosts through the periodic rule, in the launch shapes of the
+    committed autotuning cache, graph-replayed: 16 sampled blocks (4 per
+    size) against the oracle's step of the same blocks."""
+    import os
+    Z = z4c()
+    bt = W.config4()
+    O.ghost_fill(bt, bt.u)
+    note("level set SSPRK3 graph step, 16 sampled blocks")
+    Z.set_tune_cache(os.path.join(os.path.dirname(Z.__file__), "tune_gfx950.txt"))
+    try:
+        plan = Z.plan_for(bt)
+        regs = [dev(bt.u), dev(bt.u), dev(bt.u), zeros(bt.total_u)]
+        plan.set_halo(Z.GHOST_PERIODIC)
+        plan.autotune(regs[0], regs[1], regs[3], None, reps=3)
+        res = plan.step(regs, None, Z.SSPRK3, bt.dt, Z.GHOST_PERIODIC, None, graph=True)
+        got = host(regs[res])
+        plan.close()
+    finally:
+        Z.set_tune_cache(None)
+    sizes = np.array([b.nx for b in bt.blocks])
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.choice(np.nonzero(sizes == s)[0], size=4, replace=False)
+                          for s in (8, 16, 24, 32)])
+    sub = bt.subset(idx)
+    o64 = O.rk_step(sub, sub.u.copy(), table=O.SSPRK3, dt=bt.dt)
+    o80 = O.rk_step(sub, sub.u.copy(), table=O.SSPRK3, dt=bt.dt, ext=True)
+    gsub = bt.subset(idx)
+    for j, i in enumerate(idx):
+        for f in range(W.NF):
+            gsub.view(gsub.u, j, f)[...] = bt.view(got, i, f)
+    rows = compare(sub, gsub.u, o64, o80, base=sub.u)
+    assert_parity(rows, "level set ssprk3 sampled step increments\n" + report(rows))
+
 def test_config5_reduced_neighbour_step():
     Z = z4c()
     bt = W.config5(n=24)
