@@ -102,6 +102,9 @@ def lib(ext=False):
         L.orc_derivs.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, dp, dp]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_lopsided_weights.argtypes = [ctypes.c_int, dp]
+        L.orc_sommerfeld.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp, dp,
+                                     ctypes.POINTER(_RK), ctypes.c_double]
         _libs[ext] = L
     return _libs[ext]
 
@@ -199,9 +202,38 @@ def derivs(block, field: np.ndarray, fd_order: int, ko_sigma: float = 1.0) -> np
     return out.reshape(12, block.nz, block.ny, block.nx)
 
 
+def _sommerfeld(batch, u0, rhs, u0_out, u1, u2, coeffs, dt, params, ext):
+    nbr = np.ascontiguousarray(batch.neighbours, dtype=np.int32)
+    x0 = np.ascontiguousarray(batch.origins())
+    tab = batch.block_table()
+    P = _params(params or batch.params)
+    c = _RK(**(coeffs or RK4[0]))
+    lib(ext).orc_sommerfeld(ctypes.byref(P), tab.ctypes.data, len(batch.blocks),
+                            nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(x0), _dp(u0),
+                            _dp(rhs), _dp(u0_out), _dp(u1), _dp(u2), ctypes.byref(c), float(dt))
+
+
+def sommerfeld_rhs(batch, u=None, params=None, ext=False) -> np.ndarray:
+    """Radiative-law d_t u at the outer ghost points (neighbour entry -1) of
+    every block; every other entry of the result is 0."""
+    u = batch.u if u is None else u
+    out = np.zeros_like(u)
+    _sommerfeld(batch, u, out, None, None, None, None, 0.0, params, ext)
+    return out
+
+
+def sommerfeld_stage(batch, u0, u0_out, u1, u2, coeffs: dict, dt: float, params=None,
+                     ext=False):
+    """One Runge-Kutta stage of the outer ghost points by the radiative law
+    (combination and enforcement as rk_stage); other points are untouched."""
+    _sommerfeld(batch, u0, None, u0_out, u1, u2, coeffs, dt, params, ext)
+
+
 def rk_step(batch, u, table=None, dt=None, params=None, nthreads: int = 0, ext: bool = False):
     """One full Runge-Kutta step of every block with the ghost policy of the
-    batch applied after each stage.  Returns the new state (a new array)."""
+    batch applied after each stage (with batch.sommerfeld, the outer ghost
+    points advance by the radiative law in every stage first).  Returns the
+    new state (a new array)."""
     table = RK4 if table is None else table
     dt = batch.dt if dt is None else dt
     y = u
@@ -210,6 +242,10 @@ def rk_step(batch, u, table=None, dt=None, params=None, nthreads: int = 0, ext: 
     for s, c in enumerate(table):
         nxt = cur.copy()   # ghosts carried over, interior overwritten
         rk_stage(batch, cur, nxt, u1, y, c, dt, params=params, nthreads=nthreads, ext=ext)
+        if getattr(batch, "sommerfeld", False):
+            if batch.frozen is not None:
+                raise ValueError("radiative outer ghosts and a frozen array exclude each other")
+            sommerfeld_stage(batch, cur, nxt, u1, y, c, dt, params=params, ext=ext)
         ghost_fill(batch, nxt)
         cur = nxt
     return cur

@@ -883,6 +883,103 @@ int orc_ghost_fill(int policy, const orc_block *blocks, int nb, const int *nbr, 
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Radiative (Sommerfeld) outer boundary.  The paper states no outer boundary
+ * condition for Z4c; this is the usual radiative law of moving-puncture
+ * codes, taken as a reading:
+ *   outer points: the ghost points of block b in a direction (ox, oy, oz)
+ *     whose neighbour entry nbr[b*27 + dir] is -1;
+ *   at an outer point with coordinates x (x0 of the block, the coordinates
+ *     of its interior point (0,0,0), plus index times spacing) and r = |x|,
+ *     every field u evolves by
+ *       d_t u = -(x^a / r) D_a u - (u - u_inf) / r,
+ *     u_inf its flat-space value (1 for chi, gt_xx, gt_yy, gt_zz, alpha; 0
+ *     otherwise), D_a the second-order difference along a: centred where
+ *     the point's index along a lies in [0, n_a), one-sided towards the
+ *     interior otherwise;
+ *   the outer points then take the same Runge-Kutta stage and enforcement
+ *     as the interior points (orc_rk_stage); no dissipation.
+ * ------------------------------------------------------------------------ */
+static real flat_value(int f)
+{
+    return (f == CHI || f == GXX || f == GYY || f == GZZ || f == ALPHA) ? 1.0 : 0.0;
+}
+
+/* Second-order difference along one direction at index i of n interior
+ * points (stride s between neighbours, spacing h), in differences from the
+ * centre. */
+static real d1_radiative(const double *u, long s, int i, int n, real h)
+{
+    if (i < 0)
+        return (4 * DIFF(s, 0) - DIFF(2 * s, 0)) / (2 * h);
+    if (i >= n)
+        return (-4 * DIFF(-s, 0) + DIFF(-2 * s, 0)) / (2 * h);
+    return DIFF(s, -s) / (2 * h);
+}
+
+/* rhs != NULL: d_t u at every outer point of rhs (nothing else written).
+ * rhs == NULL: one stage at the outer points, u1 <- [u1] + delta u0 +
+ * eps dt k (if write_u1), u0_out <- g1 u0 + g2 u1' + g3 u2 + beta dt k,
+ * then enforcement, as orc_rk_stage does for the interior.  x0: 3 per
+ * block. */
+int orc_sommerfeld(const orc_params *P, const orc_block *blocks, int nb, const int *nbr,
+                   const double *x0, const double *u0, double *rhs, double *u0_out, double *u1,
+                   const double *u2, const orc_rk *c, double dt)
+{
+    for (int b = 0; b < nb; ++b) {
+        const orc_block *B = &blocks[b];
+        const int ng = B->ng;
+        const int n[3] = {B->nx, B->ny, B->nz};
+        const real h[3] = {B->dx, B->dy, B->dz};
+        const long sy = B->nx + 2 * ng, sz = sy * (B->ny + 2 * ng);
+        const long st[3] = {1, sy, sz};
+        for (int k = -ng; k < B->nz + ng; ++k)
+            for (int j = -ng; j < B->ny + ng; ++j)
+                for (int i = -ng; i < B->nx + ng; ++i) {
+                    const int ox = i < 0 ? -1 : (i >= B->nx ? 1 : 0);
+                    const int oy = j < 0 ? -1 : (j >= B->ny ? 1 : 0);
+                    const int oz = k < 0 ? -1 : (k >= B->nz ? 1 : 0);
+                    if (!ox && !oy && !oz)
+                        continue;
+                    if (nbr[b * 27 + (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] >= 0)
+                        continue;
+                    const int idx[3] = {i, j, k};
+                    real X[3];
+                    for (int a = 0; a < 3; ++a)
+                        X[a] = (real)x0[3 * b + a] + idx[a] * h[a];
+                    const real r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+                    const long pt = point_index(B, i, j, k);
+                    real kf[NFIELD], v[NFIELD];
+                    for (int f = 0; f < NFIELD; ++f) {
+                        const double *cf = u0 + B->offset + (long long)f * B->field_stride + pt;
+                        real adv = 0;
+                        for (int a = 0; a < 3; ++a)
+                            adv += X[a] * d1_radiative(cf, st[a], idx[a], n[a], h[a]);
+                        kf[f] = -adv / r - ((real)cf[0] - flat_value(f)) / r;
+                    }
+                    if (rhs) {
+                        for (int f = 0; f < NFIELD; ++f)
+                            rhs[B->offset + (long long)f * B->field_stride + pt] = (double)kf[f];
+                        continue;
+                    }
+                    for (int f = 0; f < NFIELD; ++f) {
+                        const long long e = B->offset + (long long)f * B->field_stride + pt;
+                        const real a1 = c->read_u1 ? (real)u1[e] : 0;
+                        const real epsdt = (real)c->eps * (real)dt, betadt = (real)c->beta * (real)dt;
+                        const real n1 = a1 + (real)c->delta * (real)u0[e] + epsdt * kf[f];
+                        v[f] = (real)c->g1 * (real)u0[e] + (real)c->g2 * n1
+                             + (c->g3 != 0.0 ? (real)c->g3 * (real)u2[e] : 0) + betadt * kf[f];
+                        if (c->write_u1)
+                            u1[e] = (double)n1;
+                    }
+                    enforce(P, v);
+                    for (int f = 0; f < NFIELD; ++f)
+                        u0_out[B->offset + (long long)f * B->field_stride + pt] = (double)v[f];
+                }
+    }
+    return 0;
+}
+
 /* Derivative probe for the operator pins: one field array of block shape in,
  * 12 interior-sized arrays out, in order
  * D1x D1y D1z  D2xx D2xy D2xz D2yy D2yz D2zz  KOx KOy KOz   (x fastest). */

@@ -128,6 +128,9 @@ class Batch:
         self.ghost = GHOST_NONE
         self.neighbours: Optional[np.ndarray] = None   # (nb, 27) int32, -1 = outer
         self.frozen: Optional[np.ndarray] = None       # copy of u used for frozen ghosts
+        # outer ghost points (neighbour entry -1) advanced by the radiative
+        # (Sommerfeld) law in every stage instead of being frozen
+        self.sommerfeld = False
         self.dt = 0.25 * min(min(b.dx, b.dy, b.dz) for b in self.blocks)
         self.name = ""
 
@@ -156,6 +159,10 @@ class Batch:
     @property
     def nstored(self) -> int:
         return sum(b.npts for b in self.blocks)
+
+    def origins(self) -> np.ndarray:
+        """Coordinates of interior point (0, 0, 0) of every block, (nb, 3)."""
+        return np.array([(b.x0, b.y0, b.z0) for b in self.blocks], dtype=np.float64)
 
     def block_table(self) -> np.ndarray:
         """Structured array matching the C `z4c_block` descriptor."""

@@ -1,0 +1,235 @@
+"""Pins of the oracle's radiative (Sommerfeld) outer boundary (CPU).
+
+The paper states no outer boundary condition for Z4c; the oracle's reading
+is the radiative law of moving-puncture codes.  At an outer ghost point (a
+ghost point of a block in a direction whose neighbour entry is -1) with
+coordinates x and r = |x|, every field u obeys
+
+    d_t u = -(x^a / r) D_a u - (u - u_inf) / r,
+
+u_inf the flat-space value, D_a the second-order difference along a
+(centred where the point's index along a lies inside the interior range,
+one-sided towards the interior outside it).  Checked against what the
+mathematics fixes, none of it re-typed from the oracle:
+
+* quadratic data u = u_inf + q(x): second-order differences are exact for
+  quadratics, so the right-hand side is -(x . grad q)/r - q/r at every
+  outer point, to rounding, and no other point is written.  A flipped sign,
+  a missing or squared r, a wrong flat value or a wrong coordinate origin
+  or spacing fails it;
+* cubic data along one axis: the one-sided and centred differences leave
+  different remainders (-h^2/3 u''' and +h^2/6 u'''), so the remainder at
+  each outer point shows which of the two the point used;
+* data even in x on a block symmetric about x = 0: the law is even in x, so
+  mirror points must give equal right-hand sides; a one-sided difference
+  pointing away from the interior on one side breaks the symmetry;
+* an outgoing spherical wave u = u_inf + F(t - r)/r satisfies the law
+  exactly; the discrete right-hand side converges to its d_t = F'(t - r)/r
+  at order 2;
+* a stage: flat data stays flat bitwise; Euler coefficients on data whose
+  metric is delta and At = 0 give u + dt k bitwise (enforcement is then the
+  identity); the accumulator takes u1 + eps dt k.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_04989_amd import workloads as W
+
+FLAT = np.array([1.0 if n in ("chi", "gxx", "gyy", "gzz", "alpha") else 0.0 for n in W.FIELDS])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+def _batch(blocks, nbr):
+    bt = W.Batch(blocks)
+    bt.params = W.Params(fd_order=6, ko_sigma=0.5)
+    bt.ghost = W.GHOST_NEIGHBOUR
+    bt.neighbours = np.asarray(nbr, dtype=np.int32)
+    bt.sommerfeld = True
+    return bt
+
+
+def _outer_mask(bt, b):
+    """Boolean array of block b's stored shape: its outer ghost points."""
+    blk = bt.blocks[b]
+    ng = blk.ng
+    k, j, i = np.meshgrid(np.arange(blk.nz + 2 * ng) - ng, np.arange(blk.ny + 2 * ng) - ng,
+                          np.arange(blk.nx + 2 * ng) - ng, indexing="ij")
+    ox = np.where(i < 0, -1, np.where(i >= blk.nx, 1, 0))
+    oy = np.where(j < 0, -1, np.where(j >= blk.ny, 1, 0))
+    oz = np.where(k < 0, -1, np.where(k >= blk.nz, 1, 0))
+    ghost = (ox != 0) | (oy != 0) | (oz != 0)
+    d = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)
+    return ghost & (bt.neighbours[b][d] < 0)
+
+
+def _two_blocks():
+    """Two blocks side by side in x with unequal spacings, away from the origin."""
+    dx, dy, dz = 0.11, 0.07, 0.13
+    a = W.Block(6, 5, 7, 4, dx, dy, dz, 3.1, -2.3, 4.7)
+    b = W.Block(6, 5, 7, 4, dx, dy, dz, 3.1 + 6 * dx, -2.3, 4.7)
+    nbr = np.full((2, 27), -1, dtype=np.int32)
+    nbr[0, W.dir_index(1, 0, 0)] = 1
+    nbr[1, W.dir_index(-1, 0, 0)] = 0
+    return _batch([a, b], nbr)
+
+
+def test_quadratic_data_gives_the_closed_form_at_outer_points_only():
+    bt = _two_blocks()
+    rng = np.random.default_rng(5)
+    coef = []
+    for f in range(W.NF):
+        a0 = rng.uniform(-0.2, 0.2)
+        bv = rng.uniform(-0.1, 0.1, size=3)
+        C = rng.uniform(-0.05, 0.05, size=(3, 3))
+        coef.append((a0, bv, 0.5 * (C + C.T)))
+    for b, blk in enumerate(bt.blocks):
+        X, Y, Z = blk.coords()
+        for f in range(W.NF):
+            a0, bv, C = coef[f]
+            P = np.stack([X, Y, Z])
+            q = a0 + np.einsum("a...,a->...", P, bv) + np.einsum("a...,ab,b...->...", P, C, P)
+            bt.view(bt.u, b, f)[...] = FLAT[f] + q
+    k = O.sommerfeld_rhs(bt)
+    k80 = O.sommerfeld_rhs(bt, ext=True)
+    for b, blk in enumerate(bt.blocks):
+        X, Y, Z = blk.coords()
+        P = np.stack([X, Y, Z])
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        mask = _outer_mask(bt, b)
+        assert mask.sum() > 0 and not mask.all()
+        for f in range(W.NF):
+            a0, bv, C = coef[f]
+            q = a0 + np.einsum("a...,a->...", P, bv) + np.einsum("a...,ab,b...->...", P, C, P)
+            grad = bv[:, None, None, None] + 2.0 * np.einsum("ab,b...->a...", C, P)
+            want = -np.einsum("a...,a...->...", P, grad) / r - q / r
+            got = bt.view(k, b, f)
+            scale = np.abs(want[mask]).max()
+            assert np.abs(got[mask] - want[mask]).max() <= 1e-12 * scale, (b, W.FIELDS[f])
+            assert np.abs(bt.view(k80, b, f)[mask] - want[mask]).max() <= 1e-12 * scale
+            # nothing but outer points is written
+            assert np.all(got[~mask] == 0.0), (b, W.FIELDS[f])
+
+
+def _single(n=(6, 6, 6), h=(0.1, 0.1, 0.1), x0=(2.0, 1.5, 2.5), ng=4):
+    blk = W.Block(n[0], n[1], n[2], ng, h[0], h[1], h[2], *x0)
+    return _batch([blk], np.full((1, 27), -1, dtype=np.int32))
+
+
+def test_cubic_remainder_shows_one_sided_outside_and_centred_inside():
+    """u = u_inf + x^3 (x only): d_x u = 3x^2 exactly; the one-sided second-
+    order difference gives 3x^2 - 2h^2, the centred one 3x^2 + h^2."""
+    h = 0.1
+    bt = _single(h=(h, h, h))
+    blk = bt.blocks[0]
+    X, Y, Z = blk.coords()
+    for f in range(W.NF):
+        bt.view(bt.u, 0, f)[...] = FLAT[f] + X ** 3
+    k = O.sommerfeld_rhs(bt)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    mask = _outer_mask(bt, 0)
+    i = np.arange(blk.nx + 2 * blk.ng) - blk.ng
+    inside_x = ((i >= 0) & (i < blk.nx))[None, None, :]
+    dx_u = np.where(inside_x, 3 * X ** 2 + h * h, 3 * X ** 2 - 2 * h * h)
+    want = -X * dx_u / r - X ** 3 / r
+    for f in range(W.NF):
+        got = bt.view(k, 0, f)
+        assert np.abs(got[mask] - want[mask]).max() <= 1e-12 * np.abs(want[mask]).max()
+
+
+def test_mirror_symmetry_of_even_data():
+    """A block symmetric about x = 0 with data even in x: mirror points
+    (i <-> n-1-i) have equal right-hand sides."""
+    n, h = 8, 0.1
+    x0 = -(n - 1) * h / 2
+    bt = _single(n=(n, 6, 6), h=(h, 0.09, 0.12), x0=(x0, 1.3, 2.2))
+    X, Y, Z = bt.blocks[0].coords()
+    for f in range(W.NF):
+        bt.view(bt.u, 0, f)[...] = FLAT[f] + 0.3 * X ** 4 - 0.2 * X ** 2 * Y + 0.1 * Z ** 3
+    k = O.sommerfeld_rhs(bt)
+    mask = _outer_mask(bt, 0)
+    assert np.array_equal(mask, mask[:, :, ::-1])
+    for f in range(W.NF):
+        got = bt.view(k, 0, f)
+        mir = got[:, :, ::-1]
+        scale = np.abs(got[mask]).max()
+        assert np.abs(got[mask] - mir[mask]).max() <= 1e-13 * scale, W.FIELDS[f]
+
+
+def _wave_error(n, h):
+    """Max |k - d_t u| over the outer points for u = u_inf + a F(-r)/r."""
+    span = 0.8
+    bt = _single(n=(n, n, n), h=(h, h, h), x0=(2.0, 1.5, 2.5))
+    X, Y, Z = bt.blocks[0].coords()
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    F = lambda s: np.exp(-((s + 3.5) / span) ** 2)
+    dF = lambda s: -2.0 * (s + 3.5) / span ** 2 * F(s)
+    amps = np.linspace(0.5, 1.5, W.NF)
+    for f in range(W.NF):
+        bt.view(bt.u, 0, f)[...] = FLAT[f] + amps[f] * F(-r) / r
+    k = O.sommerfeld_rhs(bt)
+    mask = _outer_mask(bt, 0)
+    err = 0.0
+    for f in range(W.NF):
+        want = amps[f] * dF(-r) / r
+        err = max(err, float(np.abs(bt.view(k, 0, f)[mask] - want[mask]).max()))
+    return err
+
+
+def test_outgoing_spherical_wave_converges_at_second_order():
+    e1 = _wave_error(8, 0.1)
+    e2 = _wave_error(16, 0.05)
+    e3 = _wave_error(32, 0.025)
+    o1, o2 = math.log2(e1 / e2), math.log2(e2 / e3)
+    assert 1.8 < o1 < 2.3 and 1.8 < o2 < 2.3, (e1, e2, e3, o1, o2)
+
+
+def test_stage_flat_stays_flat_and_euler_is_u_plus_dt_k():
+    bt = _single()
+    rng = np.random.default_rng(9)
+    for f in range(W.NF):
+        bt.view(bt.u, 0, f)[...] = FLAT[f]
+    u0 = bt.u.copy()
+    out = np.full_like(u0, -7.0)
+    u1 = rng.uniform(-1, 1, size=u0.shape)
+    u1_in = u1.copy()
+    O.sommerfeld_stage(bt, u0, out, u1, u0, O.RK4[1], 0.01)
+    mask = _outer_mask(bt, 0)
+    for f in range(W.NF):
+        assert np.all(bt.view(out, 0, f)[mask] == FLAT[f])
+        assert np.all(bt.view(out, 0, f)[~mask] == -7.0)
+    assert np.array_equal(u1, u1_in)
+
+    # scalar fields carry outgoing waves; gt = delta and At = 0 exactly
+    X, Y, Z = bt.blocks[0].coords()
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    scal = [W.F[n] for n in ("chi", "Khat", "Theta", "Gx", "Gy", "Gz", "alpha", "bx", "by",
+                             "bz")]
+    for q, f in enumerate(scal):
+        bt.view(bt.u, 0, f)[...] = FLAT[f] + (0.1 + 0.05 * q) * np.exp(-(r - 4.0) ** 2) / r
+    u0 = bt.u.copy()
+    k = O.sommerfeld_rhs(bt, u0)
+    dt = 0.013
+    euler = dict(delta=0.0, eps=0.0, g1=1.0, g2=0.0, g3=0.0, beta=1.0, read_u1=0, write_u1=0)
+    out = u0.copy()
+    O.sommerfeld_stage(bt, u0, out, None, None, euler, dt)
+    for f in range(W.NF):
+        want = bt.view(u0, 0, f) + dt * bt.view(k, 0, f)
+        assert np.array_equal(bt.view(out, 0, f)[mask], want[mask]), W.FIELDS[f]
+    # accumulator of an RK4 middle stage: u1 + 0 u0 + (dt/3) k
+    u1 = rng.uniform(-1, 1, size=u0.shape)
+    u1_in = u1.copy()
+    out = u0.copy()
+    c = O.RK4[1]
+    O.sommerfeld_stage(bt, u0, out, u1, u0, c, dt)
+    epsdt = c["eps"] * dt
+    for f in range(W.NF):
+        want = bt.view(u1_in, 0, f) + c["delta"] * bt.view(u0, 0, f) + epsdt * bt.view(k, 0, f)
+        assert np.array_equal(bt.view(u1, 0, f)[mask], want[mask]), W.FIELDS[f]
+        assert np.array_equal(bt.view(u1, 0, f)[~mask], bt.view(u1_in, 0, f)[~mask])
