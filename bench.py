@@ -86,6 +86,8 @@ def parse():
                          "sources to vertices)")
     ap.add_argument("--no-lopsided", action="store_true",
                     help="skip the lopsided-advection stage timing")
+    ap.add_argument("--no-sommerfeld", action="store_true",
+                    help="skip the radiative outer boundary timing on 8 x 128^3 blocks")
     ap.add_argument("--no-intergrid", action="store_true",
                     help="skip the transfers between refinement levels")
     ap.add_argument("--intergrid-only", action="store_true",
@@ -316,6 +318,8 @@ def main():
     if not args.no_lopsided:
         out["lopsided_advection"] = lopsided_timing(bt, stream, max(3, args.steps // 2),
                                                     r64["stage_ms"][1])
+    if not args.no_sommerfeld:
+        out["sommerfeld"] = sommerfeld_timing(stream, max(5, args.steps // 2))
     if not args.no_matter:
         out["matter_coupling"] = matter_coupling(stream, args.steps)
     if not args.no_intergrid:
@@ -402,6 +406,67 @@ def lopsided_timing(bt, stream, reps, centred_ms):
            "achieved_gbs": bt.ninterior * STAGE_BYTES[1] / (med * 1e-3) / 1e9}
     plan.close()
     log(f"[bench] lopsided advection: {res}")
+    return res
+
+
+def sommerfeld_timing(stream, reps):
+    """The radiative outer boundary on the star level set (8 blocks of 128^3
+    + 4 ghosts tiling [-16, 16]^3): one radiative stage of the outer ghost
+    points (RK4 stage 2: reads u0, u1, u2, writes u1, u0', 880 algorithmic B
+    per point) against the fused interior stage of the same plan, medians
+    over `reps` launches."""
+    import numpy as np
+    import torch
+
+    from paper_2311_04989_amd import workloads as W
+    from paper_2311_04989_amd import z4c as Z
+
+    bt = W.config5()
+    bt.frozen = None
+    bt.sommerfeld = True
+    nbr = np.asarray(bt.neighbours)
+    outer = 0
+    for b, blk in enumerate(bt.blocks):
+        for d in range(27):
+            if d == 13 or nbr[b, d] >= 0:
+                continue
+            o = (d % 3 - 1, (d // 3) % 3 - 1, d // 9 - 1)
+            n = (blk.nx, blk.ny, blk.nz)
+            outer += int(np.prod([blk.ng if o[a] else n[a] for a in range(3)]))
+    plan = Z.plan_for(bt)
+    plan.set_halo(Z.GHOST_NEIGHBOUR)
+    u0 = torch.from_numpy(bt.u).to("cuda:0")
+    m = torch.from_numpy(bt.matter).to("cuda:0")
+    out, u1 = u0.clone(), u0.clone()
+    calls = {
+        "radiative_stage_ms": lambda: plan.sommerfeld_stage(u0, out, u1, u0, Z.RK4[1], bt.dt,
+                                                            stream=stream),
+        "interior_stage_ms": lambda: plan.rk_stage(u0, out, u1, u0, m, Z.RK4[1], bt.dt,
+                                                   stream=stream),
+    }
+    res = {"workload": "star level set 8 x 128^3 + 4 ghosts tiling [-16, 16]^3, radiative "
+                       "outer ghosts (every ghost region without a neighbour), RK4 stage 2",
+           "outer_points": outer, "interior_points": bt.ninterior}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        res[name] = float(np.median(ms))
+    res["algorithmic_bytes"] = outer * STAGE_BYTES[1]
+    res["achieved_gbs"] = res["algorithmic_bytes"] / (res["radiative_stage_ms"] * 1e-3) / 1e9
+    res["hbm_frac"] = res["achieved_gbs"] / HBM_PEAK_GBS
+    res["cost_vs_interior_stage"] = res["radiative_stage_ms"] / res["interior_stage_ms"]
+    plan.close()
+    del u0, m, out, u1
+    torch.cuda.empty_cache()
+    log(f"[bench] radiative outer boundary: {res}")
     return res
 
 

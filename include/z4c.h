@@ -29,7 +29,8 @@
  * Ownership and asynchrony
  *   - The caller owns every field array.  A plan owns only its device copy
  *     of the block table, its tile lists, scratch for norm partial sums and
- *     its captured graphs; all of it is allocated in z4c_plan_create /
+ *     its captured graphs (and the radiative boundary's outer-point list);
+ *     all of it is allocated in z4c_plan_create /
  *     z4c_plan_set_* / on the first z4c_step_graph call, never by
  *     z4c_rhs, z4c_rk_stage, z4c_constraints, z4c_ghost_fill or z4c_step.
  *   - Every compute call is asynchronous on the given HIP stream
@@ -276,6 +277,13 @@ z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *f
                                       level jumps set with
                                       z4c_plan_set_level_exchange (implies stored
                                       ghosts) */
+#define Z4C_STEP_SOMMERFELD 16     /* the outer ghost points advance by the radiative
+                                      law beside every stage (z4c_sommerfeld_stage
+                                      into the stage's output and accumulator), so
+                                      every stage reads evolved outer ghosts; needs
+                                      z4c_plan_set_sommerfeld, the neighbour policy
+                                      and no frozen array (Z4C_EINVAL), and not
+                                      Z4C_STEP_LEVEL_EXCHANGE (Z4C_ENOTSUP) */
 typedef struct {
     double *regs[4];
     const double *matter;
@@ -408,6 +416,42 @@ z4c_status z4c_restrict(const z4c_xplan *xplan, double *u, void *hip_stream);
  * points whose ghosts are then current) coarsest pair first. */
 z4c_status z4c_plan_set_level_exchange(z4c_plan *plan, const z4c_xplan *const *xplans, int n);
 
+
+/* Radiative (Sommerfeld) outer boundary.  The paper states no outer
+ * boundary condition for Z4c (its static-star test moves the outer boundary
+ * further out instead); this is the usual radiative law of moving-puncture
+ * codes, a reading.  Outer points: the ghost points of a block in every
+ * direction whose entry of the neighbour table is -1.  At an outer point
+ * with coordinates x and r = |x| each of the 22 fields u evolves by
+ *   d_t u = -(x^a / r) D_a u - (u - u_inf) / r,
+ * u_inf its flat-space value (1 for chi, gt_xx, gt_yy, gt_zz and alpha, 0
+ * otherwise), D_a the second-order difference along a: centred where the
+ * point's index along a lies in [0, n_a), one-sided towards the interior
+ * (three points) otherwise; no dissipation, FP64 whatever the plan's
+ * arithmetic.  Stencil samples at ghost points that have a neighbour are
+ * read from the neighbour when the plan reads halos through the neighbour
+ * rule (z4c_plan_set_halo), as stored otherwise (a step reads them the way
+ * its stages do).
+ * z4c_plan_set_sommerfeld: `origins` (HOST, nblocks*3 doubles, copied) are
+ * the coordinates of each block's interior point (0, 0, 0); point (i, j, k)
+ * sits at origin + (i dx, j dy, k dz).  Needs z4c_plan_set_neighbours
+ * first (a later table rebuilds the outer point list); Z4C_EINVAL when an
+ * outer point may lie within half a grid spacing of x = 0.  NULL removes
+ * the boundary.  The plan keeps the point list in device memory. */
+z4c_status z4c_plan_set_sommerfeld(z4c_plan *plan, const double *origins);
+
+/* d_t u by the radiative law at every outer point of `rhs` (device, state
+ * layout; nothing else is written); rhs must not alias u. */
+z4c_status z4c_sommerfeld_rhs(z4c_plan *plan, const double *u, double *rhs, void *stream);
+
+/* One Runge-Kutta stage of the outer points: the combination of
+ * z4c_rk_stage with k the radiative right-hand side, then the same
+ * enforcement; arguments and aliasing rules as z4c_rk_stage (no matter).
+ * Writes only outer points of u0_out and u1, and reads only u0_in, u1, u2,
+ * so it runs before or after the z4c_rk_stage of the same stage. */
+z4c_status z4c_sommerfeld_stage(z4c_plan *plan, const double *u0_in, double *u0_out, double *u1,
+                                const double *u2, const z4c_rk_coeffs *c, double dt,
+                                void *stream);
 
 const char *z4c_strerror(z4c_status status);
 const char *z4c_last_error(void);

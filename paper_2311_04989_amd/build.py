@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libz4c.so")
 SOURCES = ["z4c_variants_p6_f64.hip", "z4c_variants_p6_f32.hip", "z4c_variants_p4.hip",
            "z4c_kernels.hip", "z4c_api.hip", "z4c_matter.hip",
            "z4c_intergrid.hip", "z4c_variants_mon.hip", "z4c_variants_lop.hip",
-           "z4c_variants_naive.hip"]
+           "z4c_variants_naive.hip", "z4c_boundary.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # a*b + c fused only where one source expression says so, so that

@@ -197,6 +197,30 @@ struct z4c_plan {
     std::vector<GraphEntry> graphs;
     int version = 0;
     int num_cus = 256;
+    // host copy of the neighbour table (nblocks*27) once set
+    std::vector<int> nbr_h;
+    // radiative outer boundary (z4c_plan_set_sommerfeld): block origins and
+    // the boxes of outer ghost points, with prefix sums of their sizes
+    bool radiative = false;
+    std::vector<double> origins;
+    std::vector<OuterRegion> outer;
+    double *origins_d = nullptr;
+    OuterRegion *outer_d = nullptr;
+    long long *outer_start_d = nullptr;
+    long long total_outer = 0;
+
+    void free_outer()
+    {
+        if (origins_d)
+            (void)hipFree(origins_d);
+        if (outer_d)
+            (void)hipFree(outer_d);
+        if (outer_start_d)
+            (void)hipFree(outer_start_d);
+        origins_d = nullptr;
+        outer_d = nullptr;
+        outer_start_d = nullptr;
+    }
 
     void free_groups()
     {
@@ -226,6 +250,116 @@ struct z4c_plan {
 };
 
 namespace {
+
+// Boxes of outer ghost points of every block under the neighbour table
+// `nbr`: the ghost region of each direction whose entry is -1.  Fails when
+// a box comes within half a grid spacing of the coordinate origin (the
+// radiative law divides by r).
+z4c_status outer_regions(const z4c_plan *P, const int *nbr, const double *origins,
+                         std::vector<OuterRegion> &out)
+{
+    out.clear();
+    for (int b = 0; b < P->nblocks; ++b) {
+        const z4c_block &B = P->blocks[b];
+        const int n[3] = {B.nx, B.ny, B.nz};
+        const double h[3] = {B.dx, B.dy, B.dz};
+        for (int d = 0; d < 27; ++d) {
+            if (d == 13 || nbr[b * 27 + d] >= 0)
+                continue;
+            const int o[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+            OuterRegion R{};
+            R.block = b;
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                R.lo[a] = o[a] < 0 ? -B.ng : (o[a] > 0 ? n[a] : 0);
+                R.n[a] = o[a] != 0 ? B.ng : n[a];
+                const double x_lo = origins[3 * b + a] + R.lo[a] * h[a];
+                const double x_hi = origins[3 * b + a] + (R.lo[a] + R.n[a] - 1) * h[a];
+                const double c = x_lo > 0.0 ? x_lo : (x_hi < 0.0 ? x_hi : 0.0);
+                d2 += c * c;
+            }
+            const double hmin = std::min(h[0], std::min(h[1], h[2]));
+            if (!(std::sqrt(d2) >= 0.5 * hmin)) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf, "block %d: outer ghost points within half a grid "
+                              "spacing of the coordinate origin (the radiative law divides by "
+                              "r)", b);
+                return fail(Z4C_EINVAL, buf);
+            }
+            out.push_back(R);
+        }
+    }
+    return Z4C_OK;
+}
+
+// Upload the radiative boundary's tables (origins, boxes, prefix sums).
+z4c_status upload_outer(z4c_plan *P)
+{
+    P->total_outer = 0;
+    std::vector<long long> start(P->outer.size() + 1, 0);
+    for (size_t q = 0; q < P->outer.size(); ++q) {
+        const OuterRegion &R = P->outer[q];
+        start[q + 1] = start[q] + (long long)R.n[0] * R.n[1] * R.n[2];
+    }
+    P->total_outer = start.back();
+    if (!P->device)
+        return Z4C_OK;
+    P->clear_graphs();
+    P->free_outer();
+    HIP_TRY(hipMalloc(&P->origins_d, sizeof(double) * 3 * P->nblocks), "hipMalloc(origins)");
+    HIP_TRY(hipMemcpy(P->origins_d, P->origins.data(), sizeof(double) * 3 * P->nblocks,
+                      hipMemcpyHostToDevice), "hipMemcpy(origins)");
+    HIP_TRY(hipMalloc(&P->outer_start_d, sizeof(long long) * start.size()),
+            "hipMalloc(outer prefix sums)");
+    HIP_TRY(hipMemcpy(P->outer_start_d, start.data(), sizeof(long long) * start.size(),
+                      hipMemcpyHostToDevice), "hipMemcpy(outer prefix sums)");
+    if (!P->outer.empty()) {
+        HIP_TRY(hipMalloc(&P->outer_d, sizeof(OuterRegion) * P->outer.size()),
+                "hipMalloc(outer boxes)");
+        HIP_TRY(hipMemcpy(P->outer_d, P->outer.data(), sizeof(OuterRegion) * P->outer.size(),
+                          hipMemcpyHostToDevice), "hipMemcpy(outer boxes)");
+    }
+    return Z4C_OK;
+}
+
+// One radiative stage (c != nullptr) or right-hand side (rhs != nullptr) of
+// the outer ghost points; rule: samples at ghost points with a neighbour are
+// read from the neighbour (as the stage's neighbour-rule halo reads).
+z4c_status enqueue_radiative(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
+                             const double *u2, const z4c_rk_coeffs *c, double dt, double *rhs,
+                             bool rule, hipStream_t s)
+{
+    RadiativeArgs a{};
+    a.nbr = rule ? P->nbr_d : nullptr;
+    a.blocks = P->blocks_d;
+    a.origins = P->origins_d;
+    a.regions = P->outer_d;
+    a.start = P->outer_start_d;
+    a.nregions = (int)P->outer.size();
+    a.total = P->total_outer;
+    a.u = u0_in;
+    a.rhs = rhs;
+    a.chi_floor = P->params.chi_floor;
+    a.alpha_floor = P->params.alpha_floor;
+    if (c) {
+        a.out = u0_out;
+        a.u1 = u1;
+        a.u2 = u2;
+        a.delta = c->delta;
+        a.eps_dt = c->eps * dt;
+        a.g1 = c->g1;
+        a.g2 = c->g2;
+        a.g3 = c->g3;
+        a.beta_dt = c->beta * dt;
+        a.read_u1 = c->read_u1;
+        a.write_u1 = c->write_u1;
+        a.use_u2 = c->g3 != 0.0;
+    }
+    const hipError_t e = launch_radiative(a, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "radiative boundary launch");
+    return Z4C_OK;
+}
 
 z4c_status upload_factors(z4c_plan *P)
 {
@@ -545,8 +679,17 @@ z4c_status validate_step(const z4c_plan *P, const z4c_step_desc *d)
             return fail(Z4C_EINVAL, "regs[3] (accumulator) is NULL but a stage uses it");
     }
     if (d->flags & ~(Z4C_STEP_STORED_GHOSTS | Z4C_STEP_NO_FINAL_FILL | Z4C_STEP_MONITOR
-                     | Z4C_STEP_LEVEL_EXCHANGE))
+                     | Z4C_STEP_LEVEL_EXCHANGE | Z4C_STEP_SOMMERFELD))
         return fail(Z4C_EINVAL, "unknown step flags");
+    if (d->flags & Z4C_STEP_SOMMERFELD) {
+        if (!P || !P->radiative)
+            return fail(Z4C_EINVAL, "Z4C_STEP_SOMMERFELD needs z4c_plan_set_sommerfeld");
+        if (d->ghost_policy != Z4C_GHOST_NEIGHBOUR || d->frozen)
+            return fail(Z4C_EINVAL, "Z4C_STEP_SOMMERFELD needs the neighbour policy without a "
+                                    "frozen array (the outer ghosts are evolved)");
+        if (d->flags & Z4C_STEP_LEVEL_EXCHANGE)
+            return fail(Z4C_ENOTSUP, "Z4C_STEP_SOMMERFELD with Z4C_STEP_LEVEL_EXCHANGE");
+    }
     if (d->flags & Z4C_STEP_LEVEL_EXCHANGE) {
         if (!P || P->levels.empty())
             return fail(Z4C_EINVAL, "Z4C_STEP_LEVEL_EXCHANGE needs z4c_plan_set_level_exchange");
@@ -615,9 +758,19 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
         if (st != Z4C_OK)
             return st;
     }
+    // radiative outer ghosts: advanced beside every stage (both read only
+    // the stage input; the stage writes interior points, this the outer
+    // ghost points, which no ghost refresh then touches)
+    const bool som = (d->flags & Z4C_STEP_SOMMERFELD) != 0;
     for (int k = 0; k < d->nstages; ++k) {
         const double *y = d->regs[0];
         const bool mon = k == 0 && (d->flags & Z4C_STEP_MONITOR);
+        if (som) {
+            st = enqueue_radiative(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y,
+                                   &d->table[k], d->dt, nullptr, !stored, s);
+            if (st != Z4C_OK)
+                return st;
+        }
         if (stored) {
             st = enqueue_stage(P, d->regs[in[k]], d->regs[out[k]], d->regs[3], y, d->matter,
                                &d->table[k], d->dt, s, Z4C_GHOST_NONE, nullptr, mon, d->cons);
@@ -935,6 +1088,7 @@ z4c_status z4c_plan_destroy(z4c_plan *P)
             (void)hipFree(P->pt_start_d);
         if (P->nbr_d)
             (void)hipFree(P->nbr_d);
+        P->free_outer();
         if (P->count_d)
             (void)hipFree(P->count_d);
         if (P->capture_stream)
@@ -1009,6 +1163,12 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
         return fail(Z4C_ENOTSUP, "the plan reads halos through the neighbour rule, which needs "
                                  "offset + stored points <= 2^32 for every block that is another "
                                  "block's neighbour");
+    std::vector<OuterRegion> outer;
+    if (P->radiative) {
+        const z4c_status so = outer_regions(P, nbr, P->origins.data(), outer);
+        if (so != Z4C_OK)
+            return so;
+    }
     if (P->device) {
         if (!P->nbr_d)
             HIP_TRY(hipMalloc(&P->nbr_d, sizeof(int) * 27 * P->nblocks), "hipMalloc(neighbours)");
@@ -1018,8 +1178,44 @@ z4c_status z4c_plan_set_neighbours(z4c_plan *P, const int *nbr)
     }
     P->has_nbr = true;
     P->nbr32 = far32;
+    P->nbr_h.assign(nbr, nbr + 27 * (size_t)P->nblocks);
     ++P->version;
+    if (P->radiative) {
+        P->outer.swap(outer);
+        return upload_outer(P);
+    }
     return Z4C_OK;
+}
+
+z4c_status z4c_plan_set_sommerfeld(z4c_plan *P, const double *origins)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!origins) {
+        P->radiative = false;
+        P->outer.clear();
+        P->total_outer = 0;
+        if (P->device) {
+            P->clear_graphs();
+            P->free_outer();
+        }
+        ++P->version;
+        return Z4C_OK;
+    }
+    if (!P->has_nbr)
+        return fail(Z4C_EINVAL, "the radiative boundary needs z4c_plan_set_neighbours first");
+    for (int q = 0; q < 3 * P->nblocks; ++q)
+        if (!std::isfinite(origins[q]))
+            return fail(Z4C_EINVAL, "origins must be finite");
+    std::vector<OuterRegion> outer;
+    const z4c_status st = outer_regions(P, P->nbr_h.data(), origins, outer);
+    if (st != Z4C_OK)
+        return st;
+    P->origins.assign(origins, origins + 3 * (size_t)P->nblocks);
+    P->outer.swap(outer);
+    P->radiative = true;
+    ++P->version;
+    return upload_outer(P);
 }
 
 z4c_status z4c_plan_set_halo(z4c_plan *P, int policy, const double *frozen)
@@ -1197,6 +1393,41 @@ z4c_status z4c_ghost_fill(z4c_plan *P, int policy, double *u, const double *froz
     if (st != Z4C_OK)
         return st;
     return enqueue_ghost(P, policy, u, frozen, (hipStream_t)stream);
+}
+
+z4c_status z4c_sommerfeld_rhs(z4c_plan *P, const double *u, double *rhs, void *stream)
+{
+    if (!P)
+        return fail(Z4C_EINVAL, "plan is NULL");
+    if (!P->radiative)
+        return fail(Z4C_EINVAL, "z4c_plan_set_sommerfeld has not been called");
+    if (!u || !rhs)
+        return fail(Z4C_EINVAL, "u and rhs must not be NULL");
+    if (u == rhs)
+        return fail(Z4C_EINVAL, "rhs must not alias u");
+    if (!aligned8(u) || !aligned8(rhs))
+        return fail(Z4C_EALIGN, "arrays must be 8-byte aligned");
+    z4c_status st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_radiative(P, u, nullptr, nullptr, nullptr, nullptr, 0.0, rhs,
+                             P->halo == Z4C_GHOST_NEIGHBOUR, (hipStream_t)stream);
+}
+
+z4c_status z4c_sommerfeld_stage(z4c_plan *P, const double *u0_in, double *u0_out, double *u1,
+                                const double *u2, const z4c_rk_coeffs *c, double dt,
+                                void *stream)
+{
+    z4c_status st = validate_stage(P, u0_in, u0_out, u1, u2, nullptr, c, dt);
+    if (st != Z4C_OK)
+        return st;
+    if (!P->radiative)
+        return fail(Z4C_EINVAL, "z4c_plan_set_sommerfeld has not been called");
+    st = need_device(P);
+    if (st != Z4C_OK)
+        return st;
+    return enqueue_radiative(P, u0_in, u0_out, u1, u2, c, dt, nullptr,
+                             P->halo == Z4C_GHOST_NEIGHBOUR, (hipStream_t)stream);
 }
 
 z4c_status z4c_step(z4c_plan *P, const z4c_step_desc *d, int *result, void *stream)

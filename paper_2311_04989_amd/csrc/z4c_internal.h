@@ -69,6 +69,35 @@ struct GhostArgs {
     int policy;
 };
 
+// Radiative (Sommerfeld) outer boundary: one box of outer ghost points of a
+// block (ghost points in a direction whose neighbour entry is -1).
+struct OuterRegion {
+    int block;
+    int lo[3];   // first point, indices counted from the first interior point
+    int n[3];    // extent per direction
+};
+
+struct RadiativeArgs {
+    const z4c_block *blocks;
+    const double *origins;        // 3 per block: coordinates of interior point (0, 0, 0)
+    const OuterRegion *regions;
+    const long long *start;       // nregions + 1 prefix sums of points
+    int nregions;
+    long long total;
+    const double *u;              // input state
+    double *rhs;                  // right-hand side mode: d_t u at the outer points
+    double *out;                  // stage mode (rhs == nullptr): u0_out
+    double *u1;
+    const double *u2;
+    double delta, eps_dt, g1, g2, g3, beta_dt;
+    int read_u1, write_u1, use_u2;
+    double chi_floor, alpha_floor;
+    // non-null: stencil samples at ghost points that have a neighbour are
+    // read from the neighbour (the neighbour rule of the stage's halo
+    // reads); null: every sample is the stored value
+    const int *nbr;
+};
+
 // Stencil scale factors of one block, in order d1[3], d2[3], mix[3] (xy, xz,
 // yz), ko[3]:  d1 = 1/(c1 h), d2 = 1/(c2 h^2), mix = d1_a d1_b,
 // ko = (-1)^(r+1) sigma / (2^(2r) h), with (c1, c2) = (12, 12) for order 4 and
@@ -97,6 +126,8 @@ hipError_t launch_naive(int fd_order, int tx, int ty, int tz, int w, const Stage
 hipError_t launch_monitor(int fd_order, int tx, int ty, int tz, int w, const StageArgs &a,
                           hipStream_t s);
 hipError_t launch_ghost(const GhostArgs &g, long long total_ghost, hipStream_t s);
+// Radiative outer boundary (z4c_boundary.hip).
+hipError_t launch_radiative(const RadiativeArgs &a, hipStream_t s);
 hipError_t launch_norm_reduce(const z4c_block *blocks, int nblocks, const long long *tile_start,
                               const int *tile_count, const double *partial, double *norms,
                               hipStream_t s);

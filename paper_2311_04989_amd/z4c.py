@@ -23,6 +23,7 @@ ADVECT_CENTRED, ADVECT_LOPSIDED = 0, 1
 GHOST_NONE, GHOST_PERIODIC, GHOST_NEIGHBOUR, GHOST_FROZEN = 0, 1, 2, 3
 PLAN_NO_DEVICE = 1
 STEP_STORED_GHOSTS, STEP_NO_FINAL_FILL, STEP_MONITOR, STEP_LEVEL_EXCHANGE = 1, 2, 4, 8
+STEP_SOMMERFELD = 16
 
 
 class Params(ctypes.Structure):
@@ -171,6 +172,10 @@ def lib():
                                           ctypes.POINTER(ctypes.c_int)]
         L.z4c_restrict.argtypes = [vp, vp, vp]
         L.z4c_plan_set_level_exchange.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int]
+        L.z4c_plan_set_sommerfeld.argtypes = [vp, vp]
+        L.z4c_sommerfeld_rhs.argtypes = [vp, vp, vp, vp]
+        L.z4c_sommerfeld_stage.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(RKCoeffs),
+                                           ctypes.c_double, vp]
         L.z4c_plan_set_level_exchange.restype = st
         for name in ("z4c_xplan_create", "z4c_xplan_destroy", "z4c_prolongate", "z4c_restrict",
                      "z4c_level_transfers"):
@@ -282,6 +287,25 @@ class Plan:
         self._levels = list(xplans)   # keep them alive while the plan uses them
         _check(lib().z4c_plan_set_level_exchange(self._h, arr, len(xplans)))
 
+    def set_sommerfeld(self, origins):
+        """Radiative outer boundary: coordinates of every block's interior
+        point (0, 0, 0), shape (nblocks, 3); None removes it."""
+        if origins is None:
+            _check(lib().z4c_plan_set_sommerfeld(self._h, None))
+            return
+        o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1)
+        if o.size != 3 * self.nblocks:
+            raise ValueError("origins must hold 3 coordinates per block")
+        _check(lib().z4c_plan_set_sommerfeld(self._h, o.ctypes.data))
+
+    def sommerfeld_rhs(self, u, rhs, stream=None):
+        _check(lib().z4c_sommerfeld_rhs(self._h, _ptr(u), _ptr(rhs), _stream(stream)))
+
+    def sommerfeld_stage(self, u0_in, u0_out, u1, u2, coeffs, dt, stream=None):
+        c = _coeffs(coeffs)
+        _check(lib().z4c_sommerfeld_stage(self._h, _ptr(u0_in), _ptr(u0_out), _ptr(u1),
+                                          _ptr(u2), ctypes.byref(c), float(dt), _stream(stream)))
+
     def set_launch(self, nx, ny, nz, tile=(8, 8, 8), persistent=0, waves=2):
         L = Launch(tile[0], tile[1], tile[2], persistent, waves)
         _check(lib().z4c_plan_set_launch(self._h, nx, ny, nz, ctypes.byref(L)))
@@ -363,6 +387,8 @@ def plan_for(batch, arith: int = ARITH_FP64, flags: int = 0) -> Plan:
     p = Plan(make_params(batch.params, arith), make_blocks(batch.block_table()), flags)
     if batch.neighbours is not None:
         p.set_neighbours(batch.neighbours)
+        if getattr(batch, "sommerfeld", False):
+            p.set_sommerfeld(batch.origins())
     return p
 
 

@@ -31,18 +31,42 @@ import numpy as np
 from paper_2311_04989_amd import workloads as W
 
 
+def outer_masks(batch):
+    """Per block, a boolean array of its stored shape marking the outer ghost
+    points: ghost points in a direction whose neighbour entry is -1."""
+    out = []
+    for b, blk in enumerate(batch.blocks):
+        ng = blk.ng
+        k, j, i = np.meshgrid(np.arange(blk.nz + 2 * ng) - ng, np.arange(blk.ny + 2 * ng) - ng,
+                              np.arange(blk.nx + 2 * ng) - ng, indexing="ij")
+        ox = np.where(i < 0, -1, np.where(i >= blk.nx, 1, 0))
+        oy = np.where(j < 0, -1, np.where(j >= blk.ny, 1, 0))
+        oz = np.where(k < 0, -1, np.where(k >= blk.nz, 1, 0))
+        ghost = (ox != 0) | (oy != 0) | (oz != 0)
+        d = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)
+        out.append(ghost & (np.asarray(batch.neighbours)[b][d] < 0))
+    return out
+
+
 def compare(batch, gpu, o64, o80, nfields=W.NF, base=None, blocks=None, names=None,
-            rel_floor=1e-3, gate=1e-12):
+            rel_floor=1e-3, gate=1e-12, masks=None):
+    """Rows (field, e_gpu, e_oracle64, tol, max|o|) over the interior points,
+    or, with `masks` (per block, a boolean array of the stored shape), over
+    the marked points."""
     names = names or (W.FIELDS if nfields == W.NF else W.CONSTRAINTS)
     blocks = range(len(batch.blocks)) if blocks is None else blocks
+    if masks is None:
+        pick = lambda arr, b, f: batch.interior(arr, b, f, nfields).ravel()
+    else:
+        pick = lambda arr, b, f: batch.view(arr, b, f, nfields)[masks[b]]
     rows = []
     for f in range(nfields):
-        g = np.concatenate([batch.interior(gpu, b, f, nfields).ravel() for b in blocks])
-        c = np.concatenate([batch.interior(o64, b, f, nfields).ravel() for b in blocks])
-        o = np.concatenate([batch.interior(o80, b, f, nfields).ravel() for b in blocks])
+        g = np.concatenate([pick(gpu, b, f) for b in blocks])
+        c = np.concatenate([pick(o64, b, f) for b in blocks])
+        o = np.concatenate([pick(o80, b, f) for b in blocks])
         allow = 0.0
         if base is not None:
-            z = np.concatenate([batch.interior(base, b, f, nfields).ravel() for b in blocks])
+            z = np.concatenate([pick(base, b, f) for b in blocks])
             allow = 4.0 * np.spacing(np.abs(o))
             g, c, o = g - z, c - z, o - z
         m = np.abs(o).max()

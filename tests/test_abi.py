@@ -429,3 +429,74 @@ def test_step_monitor_validation():
             q.step(regs, None, Z.RK4, 0.1, Z.GHOST_NONE, flags=Z.STEP_MONITOR, cons=E, norms=F)
         assert e.value.status == Z.ENOTSUP, kw
         q.close()
+
+
+def test_sommerfeld_validation():
+    """Radiative outer boundary: needs the neighbour table first, refuses
+    outer points at the coordinate origin, a later neighbour table is checked
+    the same way; the calls and the step flag validate their arguments
+    before the device check."""
+    blk = W.Block(6, 6, 6, 4, 0.1, 0.1, 0.1, 2.0, 1.5, 2.5)
+    bt = W.Batch([blk, W.Block(6, 6, 6, 4, 0.1, 0.1, 0.1, 2.6, 1.5, 2.5)])
+    bt.params = W.Params(fd_order=6)
+    nbr = np.full((2, 27), -1, dtype=np.int32)
+    nbr[0, W.dir_index(1, 0, 0)] = 1
+    nbr[1, W.dir_index(-1, 0, 0)] = 0
+    p = _plan(bt)
+    A, B, C, D = 0x10000, 0x20000, 0x30000, 0x40000
+    with pytest.raises(Z.Z4cError) as e:           # no neighbour table yet
+        p.set_sommerfeld(bt.origins())
+    assert e.value.status == Z.EINVAL
+    p.set_neighbours(nbr)
+    with pytest.raises(Z.Z4cError) as e:           # not set: calls refused
+        p.sommerfeld_rhs(A, B)
+    assert e.value.status == Z.EINVAL
+    with pytest.raises(Z.Z4cError) as e:
+        p.step([A, B, C, D], None, Z.RK4, 0.01, Z.GHOST_NEIGHBOUR, flags=Z.STEP_SOMMERFELD)
+    assert e.value.status == Z.EINVAL
+    bad = bt.origins().copy()
+    bad[0] = (0.4, -0.3, -0.3)                     # block 0's -x ghosts reach x = 0
+    with pytest.raises(Z.Z4cError) as e:
+        p.set_sommerfeld(bad)
+    assert e.value.status == Z.EINVAL
+    bad[0] = (np.nan, 0.0, 0.0)
+    with pytest.raises(Z.Z4cError) as e:
+        p.set_sommerfeld(bad)
+    assert e.value.status == Z.EINVAL
+    p.set_sommerfeld(bt.origins())
+    cases = [(lambda: p.sommerfeld_rhs(A, A), Z.EINVAL), (lambda: p.sommerfeld_rhs(A, 0), Z.EINVAL),
+             (lambda: p.sommerfeld_rhs(A, B + 4), Z.EALIGN), (lambda: p.sommerfeld_rhs(A, B), Z.ENODEV),
+             (lambda: p.sommerfeld_stage(A, A, C, D, Z.RK4[1], 0.01), Z.EINVAL),
+             (lambda: p.sommerfeld_stage(A, B, None, D, Z.RK4[1], 0.01), Z.EINVAL),
+             (lambda: p.sommerfeld_stage(A, B, C, D, Z.RK4[1], float("nan")), Z.EINVAL),
+             (lambda: p.sommerfeld_stage(A, B, C, D, Z.RK4[1], 0.01), Z.ENODEV)]
+    for call, status in cases:
+        with pytest.raises(Z.Z4cError) as e:
+            call()
+        assert e.value.status == status, e.value
+    regs = [A, B, C, D]
+    step_cases = [(dict(ghost=Z.GHOST_PERIODIC), Z.EINVAL),
+                  (dict(ghost=Z.GHOST_NEIGHBOUR, frozen=0x50000), Z.EINVAL),
+                  (dict(ghost=Z.GHOST_NEIGHBOUR), Z.ENODEV)]
+    for kw, status in step_cases:
+        ghost = kw.pop("ghost")
+        with pytest.raises(Z.Z4cError) as e:
+            p.step(regs, None, Z.RK4, 0.01, ghost, flags=Z.STEP_SOMMERFELD, **kw)
+        assert e.value.status == status, (ghost, kw, e.value)
+    # a neighbour table that exposes block 0 to the origin is refused, plan unchanged
+    far = W.Batch([W.Block(6, 6, 6, 4, 0.1, 0.1, 0.1, 0.2, -0.2, -0.2),
+                   W.Block(6, 6, 6, 4, 0.1, 0.1, 0.1, -0.4, -0.2, -0.2)])
+    far.params = W.Params(fd_order=6)
+    q = _plan(far)
+    inner = np.full((2, 27), -1, dtype=np.int32)
+    inner[0, W.dir_index(-1, 0, 0)] = 1
+    inner[1, W.dir_index(1, 0, 0)] = 0
+    q.set_neighbours(inner)                        # x = 0 is an interior point of block 1
+    q.set_sommerfeld(far.origins())
+    with pytest.raises(Z.Z4cError) as e:
+        q.set_neighbours(np.full((2, 27), -1, dtype=np.int32))
+    assert e.value.status == Z.EINVAL
+    q.set_sommerfeld(None)
+    q.set_neighbours(np.full((2, 27), -1, dtype=np.int32))
+    q.close()
+    p.close()

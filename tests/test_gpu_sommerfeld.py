@@ -1,0 +1,158 @@
+"""Radiative (Sommerfeld) outer boundary on the GPU against the oracle.
+
+Workload: the star level set reduced to 8 blocks of 24^3 + 4 ghosts tiling
+[-16, 16]^3 (star metric, matter blobs, 1e-6 noise), neighbour copies
+between the blocks and the outer ghost points (the ghost regions of every
+direction without a neighbour) advanced by the radiative law instead of
+being frozen.  Checked with the parity metric of tests/parity.py:
+* the radiative right-hand side at every outer point (nothing else written);
+* one radiative stage (RK4 stage 2: accumulator read and written) at the
+  outer points, as increments, other points untouched;
+* one RK4 step with Z4C_STEP_SOMMERFELD against the oracle's step that
+  advances the outer points in every stage: interior and outer points as
+  increments; halo-rule and stored-ghost forms and the graph replay
+  bitwise equal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from parity import assert_parity, compare, outer_masks, report
+from paper_2311_04989_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _batch():
+    """The reduced star level set with its neighbour ghosts refreshed (so
+    that the stored-ghost and halo-rule step forms start from the same data)
+    and its outer ghosts as generated."""
+    bt = W.config5(n=24)
+    bt.frozen = None
+    bt.sommerfeld = True
+    O.ghost_fill(bt, bt.u)
+    return bt
+
+
+def test_radiative_rhs_at_outer_points():
+    from paper_2311_04989_amd import z4c as Z
+    bt = _batch()
+    masks = outer_masks(bt)
+    note(f"radiative rhs: 8 x 24^3 star level set, {sum(int(m.sum()) for m in masks)} outer points")
+    plan = Z.plan_for(bt)
+    u = dev(bt.u)
+    rhs = torch.zeros_like(u)
+    plan.sommerfeld_rhs(u, rhs)
+    g = host(rhs)
+    rows = compare(bt, g, O.sommerfeld_rhs(bt), O.sommerfeld_rhs(bt, ext=True), masks=masks)
+    assert_parity(rows, "radiative rhs 8x24^3 outer points\n" + report(rows))
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            assert np.all(bt.view(g, b, f)[~masks[b]] == 0.0), (b, W.FIELDS[f])
+    # Under the neighbour rule the samples at ghost points with a neighbour
+    # come from the neighbour: stale stored values there change nothing.
+    stale = bt.u.copy()
+    for b, blk in enumerate(bt.blocks):
+        ng = blk.ng
+        inner = np.zeros(masks[b].shape, dtype=bool)
+        inner[ng:ng + blk.nz, ng:ng + blk.ny, ng:ng + blk.nx] = True
+        for f in range(W.NF):
+            bt.view(stale, b, f)[~masks[b] & ~inner] = -7.0
+    plan.set_halo(Z.GHOST_NEIGHBOUR)
+    rhs2 = torch.zeros_like(u)
+    plan.sommerfeld_rhs(dev(stale), rhs2)
+    assert np.array_equal(host(rhs2), g)
+    plan.close()
+
+
+def test_radiative_stage_at_outer_points():
+    from paper_2311_04989_amd import z4c as Z
+    bt = _batch()
+    masks = outer_masks(bt)
+    note("radiative stage (RK4 stage 2): 8 x 24^3 star level set")
+    rng = np.random.default_rng(17)
+    u0 = bt.u.copy()
+    u1_in = u0 * (1.0 + rng.uniform(-1e-3, 1e-3, size=u0.shape))
+    plan = Z.plan_for(bt)
+    gu0, gu1 = dev(u0), dev(u1_in)
+    gout = torch.full_like(gu0, -7.0)
+    plan.sommerfeld_stage(gu0, gout, gu1, gu0, Z.RK4[1], bt.dt)
+    out, u1 = host(gout), host(gu1)
+    res = {}
+    for ext in (False, True):
+        o, a1 = np.full_like(u0, -7.0), u1_in.copy()
+        O.sommerfeld_stage(bt, u0, o, a1, u0, O.RK4[1], bt.dt, ext=ext)
+        res[ext] = (o, a1)
+    rows = compare(bt, out, res[False][0], res[True][0], base=u0, masks=masks)
+    assert_parity(rows, "radiative stage u0' outer points\n" + report(rows))
+    rows = compare(bt, u1, res[False][1], res[True][1], base=u1_in, masks=masks)
+    assert_parity(rows, "radiative stage u1 outer points\n" + report(rows))
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            assert np.all(bt.view(out, b, f)[~masks[b]] == -7.0)
+            assert np.array_equal(bt.view(u1, b, f)[~masks[b]], bt.view(u1_in, b, f)[~masks[b]])
+    plan.close()
+
+
+def test_rk4_step_with_radiative_outer_ghosts():
+    from paper_2311_04989_amd import z4c as Z
+    bt = _batch()
+    masks = outer_masks(bt)
+    note("RK4 step with radiative outer ghosts: 8 x 24^3 star level set")
+    plan = Z.plan_for(bt)
+    m = dev(bt.matter)
+    finals = []
+    graph_regs = [torch.empty(bt.total_u, dtype=torch.float64, device=DEV) for _ in range(4)]
+    for flags, graph in ((0, False), (Z.STEP_STORED_GHOSTS, False), (0, True), (0, True)):
+        if graph:   # the same registers twice: the second call replays the graph
+            regs = graph_regs
+            regs[0].copy_(dev(bt.u))
+            for r in regs[1:]:
+                r.fill_(-7.0)
+        else:
+            regs = [dev(bt.u)] + [torch.full((bt.total_u,), -7.0, dtype=torch.float64,
+                                             device=DEV) for _ in range(3)]
+        note(f"  step flags {flags} graph {graph}")
+        res = plan.step(regs, m, Z.RK4, bt.dt, Z.GHOST_NEIGHBOUR, None, graph=graph,
+                        flags=flags | Z.STEP_SOMMERFELD)
+        finals.append(host(regs[res]))
+    for q in range(1, len(finals)):
+        assert np.array_equal(finals[q], finals[0]), f"step form {q} differs from the first"
+    ref64 = O.rk_step(bt, bt.u.copy())
+    ref80 = O.rk_step(bt, bt.u.copy(), ext=True)
+    rows = compare(bt, finals[0], ref64, ref80, base=bt.u)
+    assert_parity(rows, "RK4 step with radiative boundary, interior\n" + report(rows))
+    rows = compare(bt, finals[0], ref64, ref80, base=bt.u, masks=masks)
+    assert_parity(rows, "RK4 step with radiative boundary, outer points\n" + report(rows))
+    # the outer points moved (the law is not the identity on this data)
+    moved = sum(int(np.count_nonzero(bt.view(finals[0], b, W.F["chi"])[masks[b]]
+                                      != bt.view(bt.u, b, W.F["chi"])[masks[b]]))
+                for b in range(len(bt.blocks)))
+    assert moved > 0
+    plan.close()

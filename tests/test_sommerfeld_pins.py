@@ -36,6 +36,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import outer_masks
 from paper_2311_04989_amd import workloads as W
 
 FLAT = np.array([1.0 if n in ("chi", "gxx", "gyy", "gzz", "alpha") else 0.0 for n in W.FIELDS])
@@ -57,16 +58,7 @@ def _batch(blocks, nbr):
 
 def _outer_mask(bt, b):
     """Boolean array of block b's stored shape: its outer ghost points."""
-    blk = bt.blocks[b]
-    ng = blk.ng
-    k, j, i = np.meshgrid(np.arange(blk.nz + 2 * ng) - ng, np.arange(blk.ny + 2 * ng) - ng,
-                          np.arange(blk.nx + 2 * ng) - ng, indexing="ij")
-    ox = np.where(i < 0, -1, np.where(i >= blk.nx, 1, 0))
-    oy = np.where(j < 0, -1, np.where(j >= blk.ny, 1, 0))
-    oz = np.where(k < 0, -1, np.where(k >= blk.nz, 1, 0))
-    ghost = (ox != 0) | (oy != 0) | (oz != 0)
-    d = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)
-    return ghost & (bt.neighbours[b][d] < 0)
+    return outer_masks(bt)[b]
 
 
 def _two_blocks():
