@@ -89,6 +89,12 @@ def test_radiative_rhs_at_outer_points():
     plan.sommerfeld_rhs(dev(stale), rhs2)
     assert np.array_equal(host(rhs2), g)
     plan.close()
+    # the law runs in FP64 whatever the plan's arithmetic
+    p32 = Z.plan_for(bt, Z.ARITH_FP32)
+    rhs3 = torch.zeros_like(u)
+    p32.sommerfeld_rhs(u, rhs3)
+    assert np.array_equal(host(rhs3), g)
+    p32.close()
 
 
 def test_radiative_stage_at_outer_points():
