@@ -292,10 +292,10 @@ z4c_status outer_regions(const z4c_plan *P, const int *nbr, const double *origin
     return Z4C_OK;
 }
 
-// Upload the radiative boundary's tables (origins, boxes, prefix sums).
+// Upload the radiative boundary's tables (origins, boxes, prefix sums).  On
+// a failure the boundary is removed (no half-built tables stay in use).
 z4c_status upload_outer(z4c_plan *P)
 {
-    P->total_outer = 0;
     std::vector<long long> start(P->outer.size() + 1, 0);
     for (size_t q = 0; q < P->outer.size(); ++q) {
         const OuterRegion &R = P->outer[q];
@@ -306,18 +306,32 @@ z4c_status upload_outer(z4c_plan *P)
         return Z4C_OK;
     P->clear_graphs();
     P->free_outer();
-    HIP_TRY(hipMalloc(&P->origins_d, sizeof(double) * 3 * P->nblocks), "hipMalloc(origins)");
-    HIP_TRY(hipMemcpy(P->origins_d, P->origins.data(), sizeof(double) * 3 * P->nblocks,
-                      hipMemcpyHostToDevice), "hipMemcpy(origins)");
-    HIP_TRY(hipMalloc(&P->outer_start_d, sizeof(long long) * start.size()),
-            "hipMalloc(outer prefix sums)");
-    HIP_TRY(hipMemcpy(P->outer_start_d, start.data(), sizeof(long long) * start.size(),
-                      hipMemcpyHostToDevice), "hipMemcpy(outer prefix sums)");
-    if (!P->outer.empty()) {
-        HIP_TRY(hipMalloc(&P->outer_d, sizeof(OuterRegion) * P->outer.size()),
-                "hipMalloc(outer boxes)");
-        HIP_TRY(hipMemcpy(P->outer_d, P->outer.data(), sizeof(OuterRegion) * P->outer.size(),
-                          hipMemcpyHostToDevice), "hipMemcpy(outer boxes)");
+    const char *what = nullptr;
+    hipError_t e = hipMalloc(&P->origins_d, sizeof(double) * 3 * P->nblocks);
+    if (e != hipSuccess)
+        what = "hipMalloc(origins)";
+    if (!what && (e = hipMemcpy(P->origins_d, P->origins.data(), sizeof(double) * 3 * P->nblocks,
+                                hipMemcpyHostToDevice)) != hipSuccess)
+        what = "hipMemcpy(origins)";
+    if (!what && (e = hipMalloc(&P->outer_start_d, sizeof(long long) * start.size()))
+                     != hipSuccess)
+        what = "hipMalloc(outer prefix sums)";
+    if (!what && (e = hipMemcpy(P->outer_start_d, start.data(), sizeof(long long) * start.size(),
+                                hipMemcpyHostToDevice)) != hipSuccess)
+        what = "hipMemcpy(outer prefix sums)";
+    if (!what && !P->outer.empty()) {
+        if ((e = hipMalloc(&P->outer_d, sizeof(OuterRegion) * P->outer.size())) != hipSuccess)
+            what = "hipMalloc(outer boxes)";
+        else if ((e = hipMemcpy(P->outer_d, P->outer.data(), sizeof(OuterRegion) * P->outer.size(),
+                                hipMemcpyHostToDevice)) != hipSuccess)
+            what = "hipMemcpy(outer boxes)";
+    }
+    if (what) {
+        P->free_outer();
+        P->radiative = false;
+        P->outer.clear();
+        P->total_outer = 0;
+        return hip_fail(e, what);
     }
     return Z4C_OK;
 }
