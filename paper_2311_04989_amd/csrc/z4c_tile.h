@@ -539,6 +539,18 @@ __host__ __device__ constexpr int next_field(int f)
     return -1;
 }
 
+// Position of field f in the staging order (0 for the first field).
+template <int MODE>
+__host__ __device__ constexpr int stage_pos(int f)
+{
+    int g = MODE == MODE_CONS ? GXX : BETAX, p = 0;
+    while (g >= 0 && g != f) {
+        g = next_field<MODE>(g);
+        ++p;
+    }
+    return p;
+}
+
 // Fields whose u1/u2 values the one-wave stage kernel requests one stage
 // early: every field completed in its own stage (not Gamma-tilde, which is
 // completed after Theta).
@@ -1244,7 +1256,14 @@ stage_kernel(const StageArgs a)
     // one workgroup per CU: LDS for the two-pass mixed derivatives
     constexpr bool MIX2 = WPE == 1;
     using MD = MixDims<P, TX, TY, TZ>;
-    __shared__ double lds[PXY * LZ];
+    // One wave per SIMD leaves LDS room for a second halo tile: consecutive
+    // stagings alternate between the two, so a staging need not wait for
+    // every thread to finish with the previous field (the barrier after the
+    // staging before last has seen to that).  Not in the monitor and
+    // lopsided forms, whose other LDS buffers and registers it would crowd.
+    constexpr bool DBUF = MIX2 && !MON && !LOP;
+    constexpr int TILE = PXY * LZ;
+    __shared__ double lds[(DBUF ? 2 : 1) * TILE];
     __shared__ R dxb[MIX2 ? MD::NXS : 1];
     __shared__ R dyb[MIX2 ? MD::NYS : 1];
     // Per-thread LDS slots for long-lived values where the LDS that the halo
@@ -1257,7 +1276,7 @@ stage_kernel(const StageArgs a)
     // monitor: per-wave sums of |c| and c^2 of the 8 constraints
     __shared__ double mred[MON ? (NT / 64) * 16 : 1];
     constexpr int SLOT_BUDGET =
-        (LDS_PER_CU / WG_PER_CU - PXY * LZ * (int)sizeof(double) - NLD * NT * 4
+        (LDS_PER_CU / WG_PER_CU - (DBUF ? 2 : 1) * TILE * (int)sizeof(double) - NLD * NT * 4
          - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)
          - (MON ? (NT / 64) * 16 * (int)sizeof(double) : 0)) / (NT * (int)sizeof(R));
     constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
@@ -1325,8 +1344,10 @@ stage_kernel(const StageArgs a)
         auto stage = [&](auto FC) __attribute__((always_inline)) {
             constexpr int FF = decltype(FC)::value;
             constexpr int NX = next_field<MODE>(FF);
-            __syncthreads();
-            st.template store<NAIVE>(lds, t);
+            constexpr int BUF = DBUF ? (stage_pos<MODE>(FF) & 1) * TILE : 0;
+            if constexpr (!DBUF)
+                __syncthreads();
+            st.template store<NAIVE>(lds + BUF, t);
             if constexpr (NX >= 0)
                 st.prefetch(NX, t);
             const Old mine = pending;
@@ -1337,10 +1358,10 @@ stage_kernel(const StageArgs a)
             __syncthreads();
             if constexpr (MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
                                    || (FF >= BETAX && FF <= BETAZ))) {
-                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds, dxb, dyb, t);
+                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds + BUF, dxb, dyb, t);
                 __syncthreads();
             }
-            loff = tofs;
+            loff = tofs + BUF;
             asm volatile("" : "+v"(loff));
             return mine;
         };
