@@ -282,8 +282,12 @@ z4c_status z4c_ghost_fill(z4c_plan *plan, int policy, double *u, const double *f
                                       into the stage's output and accumulator), so
                                       every stage reads evolved outer ghosts; needs
                                       z4c_plan_set_sommerfeld, the neighbour policy
-                                      and no frozen array (Z4C_EINVAL), and not
-                                      Z4C_STEP_LEVEL_EXCHANGE (Z4C_ENOTSUP) */
+                                      and no frozen array (Z4C_EINVAL).  With
+                                      Z4C_STEP_LEVEL_EXCHANGE the neighbour table
+                                      is the same-level one: its -1 regions facing
+                                      another level are advanced too and then
+                                      overwritten by the exchange, so only points
+                                      no block owns keep the radiative values */
 typedef struct {
     double *regs[4];
     const double *matter;
@@ -436,8 +440,10 @@ z4c_status z4c_plan_set_level_exchange(z4c_plan *plan, const z4c_xplan *const *x
  * the coordinates of each block's interior point (0, 0, 0); point (i, j, k)
  * sits at origin + (i dx, j dy, k dz).  Needs z4c_plan_set_neighbours
  * first (a later table rebuilds the outer point list); Z4C_EINVAL when an
- * outer point may lie within half a grid spacing of x = 0.  NULL removes
- * the boundary.  The plan keeps the point list in device memory. */
+ * outer point may lie within half a grid spacing of x = 0 (in a multi-level
+ * set this covers every ghost region without a same-level neighbour,
+ * including those another level owns).  NULL removes the boundary.  The
+ * plan keeps the point list in device memory. */
 z4c_status z4c_plan_set_sommerfeld(z4c_plan *plan, const double *origins);
 
 /* d_t u by the radiative law at every outer point of `rhs` (device, state

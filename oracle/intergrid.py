@@ -188,15 +188,22 @@ def level_exchange(batch, locs, u, frozen=None, order=6, acc=np.float64):
 
 def rk_step_levels(batch, locs, u, table, dt, orc, frozen=None, order=6, ext=False):
     """One Runge-Kutta step of every block of a multi-level set with the
-    oracle's stage (`orc.rk_stage`) and, after every stage, the ghost
-    exchange `level_exchange` (one global time step for all levels).
-    Returns the new state (a new array)."""
+    oracle's stage (`orc.rk_stage`), with batch.sommerfeld the radiative
+    stage of the outer ghost points (`orc.sommerfeld_stage`, batch.neighbours
+    the same-level table), and after every stage the ghost exchange
+    `level_exchange` (one global time step for all levels).  Returns the new
+    state (a new array)."""
     y = u
     u1 = np.zeros_like(u)
     cur = u
     for c in table:
         nxt = cur.copy()
         orc.rk_stage(batch, cur, nxt, u1, y, c, dt, ext=ext)
+        if getattr(batch, "sommerfeld", False):
+            # radiative law on the ghost regions without a same-level
+            # neighbour; the exchange below overwrites those another level
+            # owns, so only points no block owns keep it
+            orc.sommerfeld_stage(batch, cur, nxt, u1, y, c, dt, ext=ext)
         nxt = level_exchange(batch, locs, nxt, frozen, order,
                              acc=np.longdouble if ext else np.float64)
         cur = nxt

@@ -701,8 +701,6 @@ z4c_status validate_step(const z4c_plan *P, const z4c_step_desc *d)
         if (d->ghost_policy != Z4C_GHOST_NEIGHBOUR || d->frozen)
             return fail(Z4C_EINVAL, "Z4C_STEP_SOMMERFELD needs the neighbour policy without a "
                                     "frozen array (the outer ghosts are evolved)");
-        if (d->flags & Z4C_STEP_LEVEL_EXCHANGE)
-            return fail(Z4C_ENOTSUP, "Z4C_STEP_SOMMERFELD with Z4C_STEP_LEVEL_EXCHANGE");
     }
     if (d->flags & Z4C_STEP_LEVEL_EXCHANGE) {
         if (!P || P->levels.empty())
@@ -773,8 +771,10 @@ z4c_status enqueue_step(z4c_plan *P, const z4c_step_desc *d, int *result, hipStr
             return st;
     }
     // radiative outer ghosts: advanced beside every stage (both read only
-    // the stage input; the stage writes interior points, this the outer
-    // ghost points, which no ghost refresh then touches)
+    // the stage input; the stage writes interior points, this the ghost
+    // points without a same-level neighbour, which the same-level refresh
+    // leaves alone; with a level exchange, the exchange then overwrites
+    // those that a block of another level owns)
     const bool som = (d->flags & Z4C_STEP_SOMMERFELD) != 0;
     for (int k = 0; k < d->nstages; ++k) {
         const double *y = d->regs[0];

@@ -11,7 +11,8 @@ being frozen.  Checked with the parity metric of tests/parity.py:
 * one RK4 step with Z4C_STEP_SOMMERFELD against the oracle's step that
   advances the outer points in every stage: interior and outer points as
   increments; halo-rule and stored-ghost forms and the graph replay
-  bitwise equal.
+  bitwise equal;
+* the same on a two-level set with the exchange across the level jump.
 """
 import sys
 
@@ -162,3 +163,67 @@ def test_rk4_step_with_radiative_outer_ghosts():
                 for b in range(len(bt.blocks)))
     assert moved > 0
     plan.close()
+
+
+def test_rk4_step_of_a_level_set_with_level_exchange_and_radiative_boundary():
+    """A two-level set (19 blocks, one level-0 block refined into 8): one RK4
+    step with the exchange across the level jump and the radiative outer
+    boundary in every stage, against the oracle step (its stage, the
+    radiative stage on the ghost regions without a same-level neighbour,
+    then its level exchange, which overwrites those that another level
+    owns).  The law's origin is the centre of a level-0 block away from the
+    refined region, so that no ghost region without a same-level neighbour
+    comes near r = 0; interior and those ghost regions are compared as
+    increments; graph replay equals the eager step."""
+    from oracle.intergrid import rk_step_levels
+    from paper_2311_04989_amd import z4c as Z
+    bt, locs = W.refined_level_set(refine=(1, 0, 0))
+    rng = np.random.default_rng(71)
+    for b, blk in enumerate(bt.blocks):
+        X, Y, Zc = blk.coords()
+        for f in range(W.NF):
+            k = 2 * np.pi * np.array([1.0, 1.5, 2.0]) * (1 + 0.1 * f)
+            base = 1.0 if W.FIELDS[f] in ("chi", "gxx", "gyy", "gzz", "alpha") else 0.0
+            bt.view(bt.u, b, f)[...] = base + 2e-3 * np.sin(k[0] * X + k[1] * Y + k[2] * Zc + f)
+    W.add_noise(bt, rng, 1e-7)
+    bt.params = W.Params(fd_order=6, ko_sigma=0.5)
+    bt.dt = 0.25 * min(b.dx for b in bt.blocks)
+    # the radiative law's origin: the centre of the level-0 block spanning
+    # [0, 0.5] x [0.5, 1] x [0.5, 1] (the refined block spans [0.5, 1] x
+    # [0, 0.5] x [0, 0.5])
+    centre = np.array([0.25, 0.75, 0.75])
+    for b in bt.blocks:
+        b.x0, b.y0, b.z0 = b.x0 - centre[0], b.y0 - centre[1], b.z0 - centre[2]
+    bt.neighbours = W.level_neighbours(bt, locs)
+    bt.frozen = None
+    bt.sommerfeld = True
+    masks = outer_masks(bt)
+    note(f"two-level set with radiative boundary: {len(bt.blocks)} blocks, "
+         f"{sum(int(m.sum()) for m in masks)} ghost points without a same-level neighbour")
+    plan = Z.plan_for(bt)
+    nlev = max(L for L, _ in locs) + 1
+    xps = []
+    for pair in range(nlev - 1):
+        pro, res = Z.level_transfers(plan, locs, pair)
+        xps.append(Z.XPlan(plan, pro, res, 6))
+    plan.set_level_exchange(xps)
+    regs = [torch.empty(bt.total_u, dtype=torch.float64, device=DEV) for _ in range(4)]
+    finals = []
+    for graph in (False, True, True):
+        regs[0].copy_(dev(bt.u))
+        for r in regs[1:]:
+            r.copy_(regs[0])
+        res = plan.step(regs, None, Z.RK4, bt.dt, Z.GHOST_NEIGHBOUR, None, graph=graph,
+                        flags=Z.STEP_LEVEL_EXCHANGE | Z.STEP_SOMMERFELD)
+        finals.append(host(regs[res]))
+    assert np.array_equal(finals[1], finals[0]) and np.array_equal(finals[2], finals[0])
+    o64 = rk_step_levels(bt, locs, bt.u, O.RK4, bt.dt, O, None, 6)
+    o80 = rk_step_levels(bt, locs, bt.u, O.RK4, bt.dt, O, None, 6, ext=True)
+    rows = compare(bt, finals[0], o64, o80, base=bt.u)
+    assert_parity(rows, "two-level RK4 step with radiative boundary, interior\n" + report(rows))
+    rows = compare(bt, finals[0], o64, o80, base=bt.u, masks=masks)
+    assert_parity(rows, "two-level RK4 step with radiative boundary, ghost regions without a "
+                  "same-level neighbour\n" + report(rows))
+    plan.close()
+    for x in xps:
+        x.close()
