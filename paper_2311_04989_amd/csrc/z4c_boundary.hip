@@ -12,10 +12,11 @@
 // range, one-sided towards the interior outside it (it reads only stored
 // points; samples at ghost points that have a neighbour are read through
 // the neighbour rule when the stage reads its halo that way, so that both
-// see the same values).  The stage combination and the enforcement (det gt = 1, tr At = 0,
-// floors) are those of the interior points; there is no dissipation.  The
-// stage kernel writes interior points and this one the outer ghost points,
-// and both read only the stage input, so the two run in either order.
+// see the same values).  The stage combination and the enforcement (det gt
+// = 1, tr At = 0, floors) are those of the interior points; there is no
+// dissipation.  The stage kernel writes interior points and this one the
+// outer ghost points, and both read only the stage input, so the two run in
+// either order.
 #include "z4c_tile.h"
 
 namespace z4c {
