@@ -160,3 +160,28 @@ def test_fp32_rhs_on_the_level_set_sampled():
             gsub.view(gsub.u, j, f)[...] = bt.view(g, i, f)
     rows = compare(sub, gsub.u, O.rhs(sub, ext="f32"), O.rhs(sub, ext=True), gate=FLOOR)
     assert_parity(rows, "fp32 level set sampled rhs (gate 8x the FP32 reference)\n" + report(rows))
+
+
+@pytest.mark.parametrize("launch", [None, ((8, 8, 4), 1)])
+def test_fp32_rhs_through_the_neighbour_rule(launch):
+    """FP32 arithmetic in the kernels that read their halo through the
+    neighbour rule (neighbour copies between the 8 blocks, frozen outer
+    faces): the GPU reads the stored state with its ghosts as generated, the
+    oracle the same state after a ghost refresh; the FP32 gate applies."""
+    from paper_2311_04989_amd import z4c as Z
+    bt = W.config5(n=16)
+    filled = bt.u.copy()
+    O.ghost_fill(bt, filled)
+    note(f"fp32 rhs config5 8x16^3 through the neighbour rule, launch {launch}")
+    plan = Z.plan_for(bt, Z.ARITH_FP32)
+    frozen = dev(bt.frozen)
+    plan.set_halo(Z.GHOST_NEIGHBOUR, frozen)
+    if launch is not None:
+        plan.set_launch(0, 0, 0, launch[0], 0, launch[1])
+    out = torch.zeros(bt.total_u, dtype=torch.float64, device="cuda:0")
+    plan.rhs(dev(bt.u), dev(bt.matter), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    plan.close()
+    rows = compare(bt, g, O.rhs(bt, filled, ext="f32"), O.rhs(bt, filled, ext=True), gate=FLOOR)
+    assert_parity(rows, f"fp32 config5 neighbour rule rhs {launch}\n" + report(rows))
