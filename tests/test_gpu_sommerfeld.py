@@ -12,7 +12,8 @@ being frozen.  Checked with the parity metric of tests/parity.py:
   advances the outer points in every stage: interior and outer points as
   increments; halo-rule and stored-ghost forms and the graph replay
   bitwise equal;
-* the same on a two-level set with the exchange across the level jump.
+* the same on a two-level set with the exchange across the level jump;
+* one SSPRK(3,3) step.
 """
 import sys
 
@@ -227,3 +228,26 @@ def test_rk4_step_of_a_level_set_with_level_exchange_and_radiative_boundary():
     plan.close()
     for x in xps:
         x.close()
+
+
+def test_ssprk3_step_with_radiative_outer_ghosts():
+    """The paper's third-order Runge-Kutta (read as SSPRK(3,3): u0 and the
+    step's start state combined, no accumulator) with the radiative outer
+    ghosts, against the oracle step."""
+    from paper_2311_04989_amd import z4c as Z
+    bt = _batch()
+    masks = outer_masks(bt)
+    note("SSPRK3 step with radiative outer ghosts: 8 x 24^3 star level set")
+    plan = Z.plan_for(bt)
+    regs = [dev(bt.u)] + [torch.full((bt.total_u,), -7.0, dtype=torch.float64, device=DEV)
+                          for _ in range(3)]
+    res = plan.step(regs, dev(bt.matter), Z.SSPRK3, bt.dt, Z.GHOST_NEIGHBOUR, None,
+                    flags=Z.STEP_SOMMERFELD)
+    got = host(regs[res])
+    ref64 = O.rk_step(bt, bt.u.copy(), table=O.SSPRK3)
+    ref80 = O.rk_step(bt, bt.u.copy(), table=O.SSPRK3, ext=True)
+    rows = compare(bt, got, ref64, ref80, base=bt.u)
+    assert_parity(rows, "SSPRK3 step with radiative boundary, interior\n" + report(rows))
+    rows = compare(bt, got, ref64, ref80, base=bt.u, masks=masks)
+    assert_parity(rows, "SSPRK3 step with radiative boundary, outer points\n" + report(rows))
+    plan.close()
