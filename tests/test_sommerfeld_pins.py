@@ -225,3 +225,24 @@ def test_stage_flat_stays_flat_and_euler_is_u_plus_dt_k():
         want = bt.view(u1_in, 0, f) + c["delta"] * bt.view(u0, 0, f) + epsdt * bt.view(k, 0, f)
         assert np.array_equal(bt.view(u1, 0, f)[mask], want[mask]), W.FIELDS[f]
         assert np.array_equal(bt.view(u1, 0, f)[~mask], bt.view(u1_in, 0, f)[~mask])
+
+
+def test_flat_two_level_set_stays_flat_through_a_step():
+    """Flat space is a fixed point of the radiative law (u = u_inf, zero
+    differences) and of the Z4c right-hand side: one RK4 step of a two-level
+    set with the radiative boundary and the exchange across the level jump
+    leaves every stored value exactly as it was."""
+    from oracle.intergrid import rk_step_levels
+    bt, locs = W.refined_level_set(refine=(1, 0, 0))
+    for b in range(len(bt.blocks)):
+        for f in range(W.NF):
+            bt.view(bt.u, b, f)[...] = FLAT[f]
+    for blk in bt.blocks:               # the law's origin inside a level-0 block
+        blk.x0, blk.y0, blk.z0 = blk.x0 - 0.25, blk.y0 - 0.75, blk.z0 - 0.75
+    bt.neighbours = W.level_neighbours(bt, locs)
+    bt.frozen = None
+    bt.sommerfeld = True
+    bt.params = W.Params(fd_order=6, ko_sigma=0.5)
+    out = rk_step_levels(bt, locs, bt.u, O.RK4, 0.25 * min(b.dx for b in bt.blocks), O, None, 6)
+    assert np.array_equal(out, bt.u)
+    assert sum(int(m.sum()) for m in outer_masks(bt)) > 0
