@@ -13,7 +13,8 @@ being frozen.  Checked with the parity metric of tests/parity.py:
   increments; halo-rule and stored-ghost forms and the graph replay
   bitwise equal;
 * the same on a two-level set with the exchange across the level jump;
-* one SSPRK(3,3) step.
+* one SSPRK(3,3) step;
+* the step flag together with the constraint monitor.
 """
 import sys
 
@@ -250,4 +251,34 @@ def test_ssprk3_step_with_radiative_outer_ghosts():
     assert_parity(rows, "SSPRK3 step with radiative boundary, interior\n" + report(rows))
     rows = compare(bt, got, ref64, ref80, base=bt.u, masks=masks)
     assert_parity(rows, "SSPRK3 step with radiative boundary, outer points\n" + report(rows))
+    plan.close()
+
+
+def test_radiative_step_with_the_constraint_monitor():
+    """Z4C_STEP_SOMMERFELD together with Z4C_STEP_MONITOR: the monitor
+    (constraints of the state the step starts from) and the new state equal
+    bitwise those of the two flags used apart."""
+    from paper_2311_04989_amd import z4c as Z
+    bt = _batch()
+    note("radiative step with the constraint monitor: 8 x 24^3 star level set")
+    plan = Z.plan_for(bt)
+    m = dev(bt.matter)
+    nb = len(bt.blocks)
+
+    def run(flags):
+        regs = [dev(bt.u)] + [torch.full((bt.total_u,), -7.0, dtype=torch.float64, device=DEV)
+                              for _ in range(3)]
+        cons = torch.zeros(bt.total_c, dtype=torch.float64, device=DEV)
+        norms = torch.zeros(16 * nb, dtype=torch.float64, device=DEV)
+        mon = flags & Z.STEP_MONITOR
+        res = plan.step(regs, m, Z.RK4, bt.dt, Z.GHOST_NEIGHBOUR, None, flags=flags,
+                        cons=cons if mon else None, norms=norms if mon else None)
+        return host(regs[res]), host(cons), host(norms)
+
+    both = run(Z.STEP_SOMMERFELD | Z.STEP_MONITOR)
+    som = run(Z.STEP_SOMMERFELD)
+    mon = run(Z.STEP_MONITOR)
+    assert np.array_equal(both[0], som[0])
+    assert np.array_equal(both[1], mon[1]) and np.array_equal(both[2], mon[2])
+    assert np.all(both[2][1::2] > 0.0)
     plan.close()
