@@ -1259,9 +1259,11 @@ stage_kernel(const StageArgs a)
     // One wave per SIMD leaves LDS room for a second halo tile: consecutive
     // stagings alternate between the two, so a staging need not wait for
     // every thread to finish with the previous field (the barrier after the
-    // staging before last has seen to that).  Not in the monitor and
-    // lopsided forms, whose other LDS buffers and registers it would crowd.
-    constexpr bool DBUF = MIX2 && !MON && !LOP;
+    // staging before last has seen to that).  In the monitor form it takes
+    // the LDS that would hold the per-thread constraint values (MSTORE);
+    // not in the lopsided form nor in the monitor form on 8x4x8 tiles, where
+    // it would push values to scratch memory (measured slower).
+    constexpr bool DBUF = MIX2 && !LOP && !(MON && TY == 4);
     constexpr int TILE = PXY * LZ;
     __shared__ double lds[(DBUF ? 2 : 1) * TILE];
     __shared__ R dxb[MIX2 ? MD::NXS : 1];
