@@ -333,6 +333,96 @@ __device__ __forceinline__ void all_ko_sums(const double *L, int off, const Fac<
     dd[4] = d1sum<P, R, TX * TY>(py) * F.mix[2];
 }
 
+// Two-pass mixed derivatives of the stage kernel, z-pass first: zs = D_z u
+// over the tile extended by Q in x and y, ys = D_y u over the tile extended
+// by Q in x (unscaled sums); then xz = D_x(zs), yz = D_y(zs), xy = D_x(ys).
+// A z plane of NR rows of at most 16 sums: even rows 16 apart from the
+// plane's start, odd rows 16 apart from an offset of 8 mod 16 (24 mod 32)
+// doubles, so that any run of two to four consecutive rows, each read at 8
+// consecutive x (the 8x8 footprint of a wave), falls in distinct LDS banks;
+// consecutive rows at a pitch of 14 or 12 sums would share banks.
+template <int NR>
+struct SumRows {
+    static constexpr int OFF = 16 * ((NR + 1) / 2) + 8;
+    static constexpr int PLANE = OFF + 16 * (NR / 2);
+    __host__ __device__ static constexpr int row(int r) { return (r & 1) * OFF + (r >> 1) * 16; }
+};
+
+template <int P, int TX, int TY, int TZ>
+struct MixDimsZ {
+    static constexpr int Q = P / 2;
+    static constexpr int EX = TX + 2 * Q, EY = TY + 2 * Q;
+    static_assert(EX <= 16, "a row of sums spans at most 16 x");
+    using ZR = SumRows<EY>;                          // z sums: EY rows per plane
+    using YR = SumRows<TY>;                          // y sums: TY rows per plane
+    static constexpr int NZS = ZR::PLANE * TZ;       // storage, in sums
+    static constexpr int NYS = YR::PLANE * TZ;
+};
+
+// The sums from the staged tile L; ZPASS: the z sums too (else they were
+// formed from the stager's registers).
+template <int P, typename R, int TX, int TY, int TZ, int PX, int PXY, bool ZPASS>
+__device__ __forceinline__ void mix_prep_z(const double *L, R *zs, R *ys, int t)
+{
+    using M = MixDimsZ<P, TX, TY, TZ>;
+    constexpr int NT = TX * TY * TZ, RAD = P / 2 + 1, Q = M::Q;
+    // 16 threads per row (those past EX idle): one row per 16 lanes
+    if constexpr (ZPASS) {
+        constexpr int NE = 16 * M::EY * TZ;
+#pragma unroll
+        for (int q = 0; q < (NE + NT - 1) / NT; ++q) {
+            const int e = t + q * NT;
+            const int ex = e % 16, r = e / 16, ey = r % M::EY, ez = r / M::EY;
+            if (((q + 1) * NT <= NE || e < NE) && ex < M::EX)
+                zs[ez * M::ZR::PLANE + M::ZR::row(ey) + ex] =
+                    d1raw<P, R, PXY>(L + (ez + RAD) * PXY + (ey - Q + RAD) * PX + (ex - Q + RAD));
+        }
+    }
+    constexpr int NE = 16 * TY * TZ;
+#pragma unroll
+    for (int q = 0; q < (NE + NT - 1) / NT; ++q) {
+        const int e = t + q * NT;
+        const int ex = e % 16, r = e / 16, ey = r % TY, ez = r / TY;
+        if (((q + 1) * NT <= NE || e < NE) && ex < M::EX)
+            ys[ez * M::YR::PLANE + M::YR::row(ey) + ex] =
+                d1raw<P, R, PX>(L + (ez + RAD) * PXY + (ey + RAD) * PX + (ex - Q + RAD));
+    }
+}
+
+// First derivative along y of the z sums at row r of a plane, from pe = the
+// sum at row r and po = the same x at row r + 1 (rows r + k: pe + 8k for even
+// k, po + 8(k - 1) for odd k); the terms as in d1sum.
+template <int P, typename R>
+__device__ __forceinline__ R d1sum_rows(const R *pe, const R *po)
+{
+    if constexpr (P == 4)
+        return R(8) * (po[0] - po[-16]) - (pe[16] - pe[-16]);
+    else
+        return R(45) * (po[0] - po[-16]) - R(9) * (pe[16] - pe[-16]) + (po[16] - po[-32]);
+}
+
+// all_ko_sums with the z-first two-pass sums.
+template <int P, typename R, int PX, int PXY, int TX, int TY, int TZ>
+__device__ __forceinline__ void all_ko_sums_z(const double *L, int off, const Fac<R> &F, R d[3],
+                                              R dd[6], R &ko, const R *zs, const R *ys, int tx,
+                                              int ty, int tz)
+{
+    using M = MixDimsZ<P, TX, TY, TZ>;
+    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
+    const Corner<CO> c{L + corner(off - CO)};
+    R kx, ky, kz;
+    axis3<P, R, 1>(c, F.d1[0], F.d2[0], F.ko[0], d[0], dd[0], kx);
+    axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], dd[3], ky);
+    axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], dd[5], kz);
+    ko = kx + ky + kz;
+    const R *pz = zs + tz * M::ZR::PLANE + M::ZR::row(ty + M::Q) + (tx + M::Q);
+    const R *pz1 = zs + tz * M::ZR::PLANE + M::ZR::row(ty + M::Q + 1) + (tx + M::Q);
+    const R *py = ys + tz * M::YR::PLANE + M::YR::row(ty) + (tx + M::Q);
+    dd[1] = d1sum<P, R, 1>(py) * F.mix[0];
+    dd[2] = d1sum<P, R, 1>(pz) * F.mix[1];
+    dd[4] = d1sum_rows<P, R>(pz, pz1) * F.mix[2];
+}
+
 // beta^k d_k of the field staged in L with lopsided derivatives.
 template <int P, typename R, int PX, int PXY>
 __device__ __forceinline__ R lop_adv(const double *L, int off, const Fac<R> &F, const R beta[3])
@@ -1255,7 +1345,7 @@ stage_kernel(const StageArgs a)
     constexpr bool EARLY_OLD = WPE == 1;
     // one workgroup per CU: LDS for the two-pass mixed derivatives
     constexpr bool MIX2 = WPE == 1;
-    using MD = MixDims<P, TX, TY, TZ>;
+    using MZ = MixDimsZ<P, TX, TY, TZ>;
     // One wave per SIMD leaves LDS room for a second halo tile: consecutive
     // stagings alternate between the two, so a staging need not wait for
     // every thread to finish with the previous field (the barrier after the
@@ -1266,8 +1356,16 @@ stage_kernel(const StageArgs a)
     constexpr bool DBUF = MIX2 && !LOP && !(MON && TY == 4);
     constexpr int TILE = PXY * LZ;
     __shared__ double lds[(DBUF ? 2 : 1) * TILE];
-    __shared__ R dxb[MIX2 ? MD::NXS : 1];
-    __shared__ R dyb[MIX2 ? MD::NYS : 1];
+    // The stager gives each thread one z-column of the halo box when the box
+    // has as many columns as the tile has points (8x8x4 tiles): the z sums
+    // of the mixed derivatives are then formed from its registers while the
+    // field is stored, into one of two alternating buffers (they are written
+    // before the staging barrier, so the buffer the previous mixed field
+    // reads must be the other one).
+    constexpr bool COLZ = MIX2 && LX * LY == NT && NLD == LZ && !NAIVE;
+    constexpr int NZB = COLZ ? 2 : 1;
+    __shared__ R zsb[MIX2 ? NZB * MZ::NZS : 1];
+    __shared__ R ysb[MIX2 ? MZ::NYS : 1];
     // Per-thread LDS slots for long-lived values where the LDS that the halo
     // tile leaves at this occupancy allows: the Christoffel symbols (from the
     // conformal metric stage to the lapse stage) and the shift gradient (from
@@ -1279,7 +1377,7 @@ stage_kernel(const StageArgs a)
     __shared__ double mred[MON ? (NT / 64) * 16 : 1];
     constexpr int SLOT_BUDGET =
         (LDS_PER_CU / WG_PER_CU - (DBUF ? 2 : 1) * TILE * (int)sizeof(double) - NLD * NT * 4
-         - (MIX2 ? (MD::NXS + MD::NYS) * (int)sizeof(R) : 0)
+         - (MIX2 ? (NZB * MZ::NZS + MZ::NYS) * (int)sizeof(R) : 0)
          - (MON ? (NT / 64) * 16 * (int)sizeof(double) : 0)) / (NT * (int)sizeof(R));
     constexpr bool GU_SLOT = SLOT_BUDGET >= 18;
     constexpr bool DB_SLOT = SLOT_BUDGET >= (GU_SLOT ? 27 : 9);
@@ -1342,14 +1440,34 @@ stage_kernel(const StageArgs a)
 
         LStager<NLD, NT, LX, LY, LZ, PX, PXY, GEN> st;
         setup_lstager<NLD, NT, RAD, LX, LY, LZ, PX, PXY, GEN>(st, src_lds, a, T, B, t);
+        // z sums of the mixed derivatives of the field staged last
+        const R *zcur = zsb;
         // Stages field FF; returns the early-loaded u1/u2 values of FF.
         auto stage = [&](auto FC) __attribute__((always_inline)) {
             constexpr int FF = decltype(FC)::value;
             constexpr int NX = next_field<MODE>(FF);
             constexpr int BUF = DBUF ? (stage_pos<MODE>(FF) & 1) * TILE : 0;
+            constexpr bool MIXF = MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
+                                           || (FF >= BETAX && FF <= BETAZ));
+            constexpr int ZB = COLZ ? (stage_pos<MODE>(FF) & 1) * MZ::NZS : 0;
             if constexpr (!DBUF)
                 __syncthreads();
             st.template store<NAIVE>(lds + BUF, t);
+            if constexpr (MIXF && COLZ) {
+                // this thread's column: (x, y) = (t mod LX, t / LX), z = q
+                constexpr int X0 = RAD - MZ::Q;
+                const int cx = t % LX - X0, cy = t / LX - X0;
+                if (cx >= 0 && cx < MZ::EX && cy >= 0 && cy < MZ::EY) {
+                    double col[LZ];
+#pragma unroll
+                    for (int q = 0; q < LZ; ++q)
+                        col[q] = st.pf[q];
+#pragma unroll
+                    for (int z = 0; z < TZ; ++z)
+                        zsb[ZB + z * MZ::ZR::PLANE + MZ::ZR::row(cy) + cx] =
+                            d1raw<P, R, 1>(col + z + RAD);
+                }
+            }
             if constexpr (NX >= 0)
                 st.prefetch(NX, t);
             const Old mine = pending;
@@ -1358,10 +1476,10 @@ stage_kernel(const StageArgs a)
                     pending = old(NX);
             }
             __syncthreads();
-            if constexpr (MIX2 && (FF == CHI || FF == ALPHA || (FF >= GXX && FF <= GZZ)
-                                   || (FF >= BETAX && FF <= BETAZ))) {
-                mix_prep<P, R, TX, TY, TZ, PX, PXY>(lds + BUF, dxb, dyb, t);
+            if constexpr (MIXF) {
+                mix_prep_z<P, R, TX, TY, TZ, PX, PXY, !COLZ>(lds + BUF, zsb + ZB, ysb, t);
                 __syncthreads();
+                zcur = zsb + ZB;
             }
             loff = tofs + BUF;
             asm volatile("" : "+v"(loff));
@@ -1377,8 +1495,8 @@ stage_kernel(const StageArgs a)
         // first and second derivatives and dissipation of the staged field
         auto derivs2 = [&](R d[3], R dd[6], R &ko) __attribute__((always_inline)) {
             if constexpr (MIX2)
-                all_ko_sums<P, R, PX, PXY, TX, TY, TZ>(lds, loff, F, d, dd, ko, dxb, dyb, tx, ty,
-                                                       tz);
+                all_ko_sums_z<P, R, PX, PXY, TX, TY, TZ>(lds, loff, F, d, dd, ko, zcur, ysb, tx,
+                                                         ty, tz);
             else
                 all_ko<P, R, PX, PXY, CHAIN>(lds, loff, F, d, dd, ko);
         };
