@@ -820,6 +820,14 @@ struct LStager {
     template <bool NAIVE = false>
     __device__ __forceinline__ void store(double *lds, int t)
     {
+        if constexpr (LX * LY == NT && NLD == LZ) {
+            // one z-column per thread: element q at z = q, PXY apart
+            double *col = lds + (t / LX) * PX + t % LX;
+#pragma unroll
+            for (int q = 0; q < NLD; ++q)
+                col[q * PXY] = NAIVE ? double(float(pf[q])) : pf[q];
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = t + q * NT;
