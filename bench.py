@@ -52,8 +52,8 @@ STAGE_BYTES = [3 * 176, 5 * 176, 5 * 176, 3 * 176]
 PROFILED_STAGE2 = {
     "tiles": {8: ((8, 8, 4), 256, 1), 16: ((8, 8, 4), 256, 1), 24: ((8, 8, 4), 256, 1),
               32: ((8, 8, 4), 256, 1)},
-    "fetch_kib": 3863125.3, "fetch_scale": 2.0,
-    "write_kib": 2653889.0, "write_scale": 1.0,
+    "fetch_kib": 3850980.8, "fetch_scale": 2.0,
+    "write_kib": 2656116.1, "write_scale": 1.0,
 }
 
 
