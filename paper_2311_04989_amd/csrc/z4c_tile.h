@@ -266,7 +266,8 @@ __device__ __forceinline__ void all_ko(const double *L, int &off, const Fac<R> &
         off = after(off, dd[4]);
 }
 
-// Mixed second derivatives in two passes (when the LDS allows): every
+// Mixed second derivatives in two passes, x/y first (the constraint
+// kernel's form; the stage kernel's z-first form follows): every
 // thread first writes unscaled x- and y-first-derivative sums of the staged
 // field over the tile extended by the stencil half width in the other
 // directions (x sums: y and z extended; y sums: z extended); after a
@@ -310,27 +311,6 @@ __device__ __forceinline__ R d1sum(const R *c)
         return R(8) * (c[ST] - c[-ST]) - (c[2 * ST] - c[-2 * ST]);
     else
         return R(45) * (c[ST] - c[-ST]) - R(9) * (c[2 * ST] - c[-2 * ST]) + (c[3 * ST] - c[-3 * ST]);
-}
-
-// As all_ko, with the mixed derivatives from the two-pass sums.
-template <int P, typename R, int PX, int PXY, int TX, int TY, int TZ>
-__device__ __forceinline__ void all_ko_sums(const double *L, int off, const Fac<R> &F, R d[3],
-                                            R dd[6], R &ko, const R *dxb, const R *dyb, int tx,
-                                            int ty, int tz)
-{
-    using M = MixDims<P, TX, TY, TZ>;
-    constexpr int CO = (P / 2 + 1) * (1 + PX + PXY);
-    const Corner<CO> c{L + corner(off - CO)};
-    R kx, ky, kz;
-    axis3<P, R, 1>(c, F.d1[0], F.d2[0], F.ko[0], d[0], dd[0], kx);
-    axis3<P, R, PX>(c, F.d1[1], F.d2[1], F.ko[1], d[1], dd[3], ky);
-    axis3<P, R, PXY>(c, F.d1[2], F.d2[2], F.ko[2], d[2], dd[5], kz);
-    ko = kx + ky + kz;
-    const R *px = dxb + ((tz + M::Q) * M::DY + (ty + M::Q)) * TX + tx;
-    const R *py = dyb + ((tz + M::Q) * TY + ty) * TX + tx;
-    dd[1] = d1sum<P, R, TX>(px) * F.mix[0];
-    dd[2] = d1sum<P, R, TX * M::DY>(px) * F.mix[1];
-    dd[4] = d1sum<P, R, TX * TY>(py) * F.mix[2];
 }
 
 // Two-pass mixed derivatives of the stage kernel, z-pass first: zs = D_z u
