@@ -317,9 +317,10 @@ __device__ __forceinline__ R d1sum(const R *c)
 // over the tile extended by Q in x and y, ys = D_y u over the tile extended
 // by Q in x (unscaled sums); then xz = D_x(zs), yz = D_y(zs), xy = D_x(ys).
 // A z plane of NR rows of at most 16 sums: even rows 16 apart from the
-// plane's start, odd rows 16 apart from an offset of 8 mod 16 (24 mod 32)
-// doubles, so that any run of two to four consecutive rows, each read at 8
-// consecutive x (the 8x8 footprint of a wave), falls in distinct LDS banks;
+// plane's start, odd rows 16 apart from an offset of 8 mod 16, so that for
+// double sums any run of two to four consecutive rows, each read at 8
+// consecutive x (the 8x8 footprint of a wave), falls in distinct LDS banks
+// (rows r..r+3 start at 0, 8, 16, 24 mod 32 doubles in some order);
 // consecutive rows at a pitch of 14 or 12 sums would share banks.
 template <int NR>
 struct SumRows {
@@ -381,7 +382,8 @@ __device__ __forceinline__ R d1sum_rows(const R *pe, const R *po)
         return R(45) * (po[0] - po[-16]) - R(9) * (pe[16] - pe[-16]) + (po[16] - po[-32]);
 }
 
-// all_ko_sums with the z-first two-pass sums.
+// As all_ko (pure derivatives and dissipation from the staged tile), with
+// the mixed derivatives from the z-first two-pass sums.
 template <int P, typename R, int PX, int PXY, int TX, int TY, int TZ>
 __device__ __forceinline__ void all_ko_sums_z(const double *L, int off, const Fac<R> &F, R d[3],
                                               R dd[6], R &ko, const R *zs, const R *ys, int tx,
